@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Throughput of the QTAM forward + inverse transform on one MI355X.
+
+Workload (the batched form): 256 segments x 131072 samples (32 s at 4096 Hz) of
+seeded coloured Gaussian noise with an injected chirp and two sine-Gaussian
+glitches each; 256 log-spaced rows from 10 to 2048 Hz; Q in {4, 8, 16}, each
+its own plan; FP32. One step = forward + inverse of the whole batch under each
+of the three plans. Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0). Extra fields: latency percentiles of a step,
+per-kernel times measured with HIP events on the launch stream, the roofline of
+the dominant kernel and of the whole path, and the FP64 CPU oracle timed on a
+bounded sample of the same workload (with the error of the GPU results on that
+sample against it).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+WORKLOAD = dict(fs=4096.0, n=131072, batch=256, rows=256, f_min=10.0, f_max=2048.0, qs=(4.0, 8.0, 16.0))
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=WORKLOAD["batch"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (profiling runs)")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_bytes(kind: str, plan, batch: int, b: int) -> float:
+    """Algorithmic bytes one launch of a kernel must move (b = bytes per real)."""
+    N, R, no, sl = plan.N, plan.R, plan.N_out, plan.info.sum_len
+    c = 2 * b
+    per_seg = {
+        "fwd_rows": R * no * c + (N // 2) * c,           # write envelopes, read the spectrum once
+        "inv_rows": R * no * c + sl * c,                 # read envelopes, write the kept slots
+        "overlap_add": sl * c + (N // 2) * c,            # read kept slots, write the half spectrum
+        "spectrum_fft": N * b + (N // 2) * c,            # read signal, write spectrum
+        "spectrum_fft_pass1": N * b + (N // 2) * c,
+        "spectrum_fft_pass2": 2 * (N // 2) * c,
+        "synthesis_fft": (N // 2) * c + N * b,
+        "synthesis_fft_pass1": 2 * (N // 2) * c,
+        "synthesis_fft_pass2": (N // 2) * c + N * b,
+    }.get(kind)
+    return None if per_seg is None else float(per_seg) * batch
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the transform shards by segment with no exchange, "
+              "and this build runs on a single MI355X; use --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2603_29785_amd as qt
+    import synthetic
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    W = WORKLOAD
+    B = args.batch
+    b = 8 if args.precision == "fp64" else 4
+    rdt = torch.float64 if args.precision == "fp64" else torch.float32
+
+    t0 = time.time()
+    x_host = synthetic.batched_segments(B, W["n"], W["fs"], dtype=np.float64)
+    x = torch.from_numpy(x_host).to(device=dev, dtype=rdt)
+    print("inputs ready in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+    plans = [qt.Plan(W["fs"], W["n"], q, W["f_min"], W["f_max"], W["rows"], precision=args.precision)
+             for q in W["qs"]]
+    n_out = plans[0].N_out
+    assert all(p.N_out == n_out for p in plans)
+    ws_bytes = max(p.workspace_bytes(B) for p in plans)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    y = torch.empty((B, W["rows"], n_out), dtype=torch.complex128 if b == 8 else torch.complex64, device=dev)
+    xr = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        for p in plans:
+            p.forward(x, out=y, ws=ws, stream=stream)
+            p.inverse(y, out=xr, ws=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    lat = np.array([a.elapsed_time(c) for a, c in ev])
+    samples_per_step = len(plans) * B * W["n"]
+    value = samples_per_step * args.steps / wall
+    ms_per_step = 1e3 * wall / args.steps
+    print("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
+
+    # whole-path roofline: algorithmic bytes 2 b N + 4 b R N_out per segment and plan
+    alg_path = len(plans) * B * (2 * b * W["n"] + 4 * b * W["rows"] * n_out)
+    path_gbs = alg_path / (ms_per_step * 1e-3) / 1e9
+
+    # per-kernel durations with HIP events on the launch stream
+    kernels = {}
+    roofline = None
+    if not args.no_kernel_timing:
+        for p in plans:
+            p.timing(True)
+        reps = max(3, min(10, args.steps))
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        for p in plans:
+            for name, (ms, cnt) in p.timing_collect().items():
+                k = kernels.setdefault(name, dict(total_ms=0.0, launches=0, bytes=0.0))
+                k["total_ms"] += ms
+                k["launches"] += cnt
+                kb = kernel_bytes(name, p, B, b)
+                k["bytes"] += (kb or 0.0) * cnt
+            p.timing(False)
+        for name, k in kernels.items():
+            k["avg_ms"] = k["total_ms"] / max(k["launches"], 1)
+            k["achieved_GBs"] = k["bytes"] / (k["total_ms"] * 1e-3) / 1e9 if k["total_ms"] > 0 else None
+        dom = max(kernels, key=lambda n: kernels[n]["total_ms"])
+        k = kernels[dom]
+        ach = k["achieved_GBs"]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "avg_launch_ms": round(k["avg_ms"], 4),
+                    "bytes_per_launch": k["bytes"] / max(k["launches"], 1)}
+
+    out = {
+        "metric": "fwd+inv QTAM samples/s @1 GPU; p50/p99 latency; recon rel-err vs FP64",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if b == 8 else "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched QTAM fwd+inv: %d segments x %d samples @ %g Hz, coloured noise + "
+                               "chirp + 2 sine-Gaussians; Q in %s (one plan each), %d rows %g-%g Hz, N_out %d"
+                               % (B, W["n"], W["fs"], list(W["qs"]), W["rows"], W["f_min"], W["f_max"], n_out),
+                   "batch": B, "n_samples": W["n"], "fs": W["fs"], "q": list(W["qs"]), "rows": W["rows"],
+                   "f_min": W["f_min"], "f_max": W["f_max"], "n_out": n_out, "precision": args.precision},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "what": "one step (3 plans x fwd+inv of the batch), HIP events"},
+        "path_roofline": {"achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(path_gbs / HBM_PEAK_GBS, 4),
+                          "bytes_per_step": alg_path},
+        "kernels": {n: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in k.items()}
+                    for n, k in kernels.items()},
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu:
+        out.update(cpu_leg(args, plans, x_host, x, B, W))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_leg(args, plans, x_host, x_dev, B, W):
+    """FP64 oracle on a bounded sample of the workload (single thread), and
+    the GPU's error against it on the same segments."""
+    import torch
+    from oracle import oracle as o
+
+    ops = [o.OraclePlan(fs=W["fs"], n=W["n"], q=q, f_min=W["f_min"], f_max=W["f_max"], rows=W["rows"])
+           for q in W["qs"]]
+    prec = plans[0].params["precision"]
+    t0 = time.perf_counter()
+    done = 0
+    errs_y, errs_x = [], []
+    seg = 0
+    while True:
+        i = (seg * 37) % B
+        p, op = plans[seg % 3], ops[seg % 3]
+        xi = x_host[i]
+        if prec == "fp32":
+            xi = xi.astype(np.float32).astype(np.float64)
+        ta = time.perf_counter()
+        Yo = op.forward(xi)
+        xo = op.inverse(Yo)
+        done += 1
+        t_oracle = time.perf_counter() - ta
+        # the GPU's results on the same segment
+        Yg = p.forward(x_dev[i:i + 1].contiguous())
+        xg = p.inverse(Yg)
+        Yg = Yg[0].cpu().numpy()
+        xg = xg[0].cpu().numpy()
+        errs_y.append(float(np.linalg.norm(Yg - Yo) / np.linalg.norm(Yo)))
+        errs_x.append(float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)))
+        seg += 1
+        elapsed = time.perf_counter() - t0
+        if elapsed >= args.cpu_seconds or seg >= 3 * B:
+            break
+        _ = t_oracle
+    # time of the oracle only (the GPU calls above are excluded by re-timing)
+    t1 = time.perf_counter()
+    n_re = min(done, 3)
+    for s in range(n_re):
+        op = ops[s % 3]
+        xi = x_host[(s * 37) % B]
+        op.inverse(op.forward(xi))
+    per_seg = (time.perf_counter() - t1) / n_re
+    cpu_value = W["n"] / per_seg
+    cpu = {"value": cpu_value, "unit": "samples/s", "cores": 1, "kind": "oracle",
+           "sample": "%d segments of %d samples (plans cycling Q=4/8/16), FP64 forward+inverse, "
+                     "single thread; rate from %d re-timed segments" % (done, W["n"], n_re),
+           "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+    return {"cpu_baseline": cpu,
+            "recon_rel_err": {"coef_max": max(errs_y), "recon_max": max(errs_x), "segments": done,
+                              "vs": "FP64 CPU oracle", "precision": prec}}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,181 @@
+/*
+ * qtam.h - C ABI of the MI355X (gfx950) QTAM library, libqtam.so.
+ *
+ * QTAM is the Q-transform with amplitude demodulation of Asprea et al.,
+ * "QTAM: Q-Transform Amplitude Modulation" (arXiv 2603.29785). For each row k
+ * of a log-spaced frequency grid the forward transform filters the real FFT of
+ * a segment with a frequency-domain window W_k, rolls the band to baseband and
+ * takes a short inverse FFT of length N_out, giving a decimated complex
+ * envelope Y_k (Sec. III; App. A). The inverse FFTs each envelope, re-modulates
+ * it to its carrier, overlap-adds W_k-weighted tiles, divides by the frame
+ * operator P = sum_k |W_k|^2 and returns to the time domain (canonical dual
+ * frame, Sec. III inverse equation; App. C).
+ *
+ * Conventions used by every entry point:
+ *   - N samples per segment (even), sample rate fs, T = N/fs seconds.
+ *   - DFT X[b] = sum_n x[n] e^{-2 pi i b n/N}, b = 0..N/2 (App. C).
+ *   - Envelope Y_k[m] = sqrt(N_out/N) (1/N_out) sum_u Z_k[u] e^{+2 pi i u m/N_out},
+ *     Z_k[j mod N_out] = X[s_k + j] W_k[s_k + j] for |j| <= h_k and
+ *     0 <= s_k + j <= N/2 (Sec. III renormalisation; App. C demodulation;
+ *     N_in is read as N). m = 0 is t = 0; no fftshift.
+ *   - Inverse x = irfft( M/P * sum_k W_k * sqrt(N/N_out) DFT_{N_out}(Y_k)[b - s_k] ),
+ *     M[b] = [P[b] >= p_floor_rel * max P] (App. C; bins no window covers, or
+ *     covers too weakly, are projected out; p_floor_rel = 0 keeps every P > 0).
+ *
+ * Layouts (all contiguous, row-major):
+ *   x : [batch, N] real (float for QTAM_FP32 plans, double for QTAM_FP64)
+ *   y : [batch, R, N_out] interleaved complex (float2 / double2)
+ *
+ * Ownership: the caller owns x, y and the workspace (device memory). A plan
+ * owns its host tables and, unless created host-only, device copies of them
+ * on the device that was current at creation; it is immutable after creation.
+ *
+ * Concurrency and errors: transform calls only enqueue work on the given HIP
+ * stream and never synchronise. Concurrent calls on one plan are legal when
+ * they use distinct workspaces. Arguments are validated before any launch;
+ * failures return a status and enqueue nothing. Launch failures are reported
+ * as QTAM_ERR_DEVICE.
+ */
+#ifndef QTAM_H
+#define QTAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qtam_plan_s* qtam_plan_t;   /* opaque, immutable after create */
+typedef void* qtam_stream_t;               /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  QTAM_OK = 0,
+  QTAM_ERR_INVALID_ARG = 1,   /* bad parameter, NULL pointer, or n_out < max L_k */
+  QTAM_ERR_UNSUPPORTED = 2,   /* valid but not implemented on the GPU (e.g. size) */
+  QTAM_ERR_WORKSPACE = 3,     /* workspace smaller than one segment needs */
+  QTAM_ERR_OOM = 4,           /* device allocation of plan tables failed */
+  QTAM_ERR_DEVICE = 5         /* HIP runtime / launch error, or no device */
+} qtam_status;
+
+typedef enum { QTAM_FP32 = 0, QTAM_FP64 = 1 } qtam_precision;
+
+/* Cap on window length L_k (App. A, max_window_size). g = ceil(T * df_max),
+ * df_max the largest gap between consecutive row frequencies.
+ *   COVER : L_max = 2g + 1 (each clamped window reaches its neighbours'
+ *           centres; no frame holes) - default
+ *   PAPER : L_max = 2 floor(g/2) + 1 (the printed formula)
+ *   NONE  : no cap (pure constant-Q)
+ *   MANUAL: L_max = params.max_window bins                                  */
+typedef enum { QTAM_CAP_COVER = 0, QTAM_CAP_PAPER = 1, QTAM_CAP_NONE = 2, QTAM_CAP_MANUAL = 3 } qtam_cap_mode;
+
+/* Window normalisation (Sec. II): unit energy per tile (default), the printed
+ * constant 1/sum W'^2, or none.                                              */
+typedef enum { QTAM_NORM_UNIT_ENERGY = 0, QTAM_NORM_PAPER_INV_ENERGY = 1, QTAM_NORM_NONE = 2 } qtam_norm_mode;
+
+/* Window shapes on x = j/h_k in [-1, 1] (Sec. II; App. A). window_param is
+ * Kaiser beta, Tukey alpha or Planck-taper alpha.                           */
+typedef enum { QTAM_WIN_BISQUARE = 0, QTAM_WIN_HANN = 1, QTAM_WIN_KAISER = 2,
+               QTAM_WIN_TUKEY = 3, QTAM_WIN_PLANCK = 4 } qtam_window;
+
+enum { QTAM_PLAN_HOST_ONLY = 1 };   /* qtam_params.flags: build tables, no device upload */
+
+typedef struct {
+  double sample_rate;       /* fs in Hz, > 0                                      */
+  int64_t n_samples;        /* N, even, >= 16                                     */
+  double q;                 /* quality factor Q = f / df, > 0                     */
+  double f_min, f_max;      /* 0 < f_min <= f_max <= fs/2 (grid ends, inclusive)  */
+  int32_t n_rows;           /* R >= 1; with freqs != NULL the list length         */
+  const double* freqs;      /* optional explicit non-decreasing centre list (App. A); copied */
+  int32_t window;           /* qtam_window                                        */
+  double window_param;
+  int32_t cap_mode;         /* qtam_cap_mode                                      */
+  int32_t max_window;       /* bins, QTAM_CAP_MANUAL only                         */
+  int32_t norm_mode;        /* qtam_norm_mode                                     */
+  int32_t n_out;            /* 0: next power of two >= max L_k; else >= max L_k   */
+  double p_floor_rel;       /* mask threshold relative to max P; default 1e-6     */
+  int32_t precision;        /* qtam_precision                                     */
+  int32_t flags;            /* QTAM_PLAN_HOST_ONLY or 0                           */
+} qtam_params;
+
+typedef struct {
+  int32_t n_rows;           /* R                                                  */
+  int32_t n_out;            /* N_out                                              */
+  int32_t max_len;          /* max_k L_k = 2 h_k + 1                              */
+  int32_t precision;
+  int64_t n_samples;        /* N                                                  */
+  int64_t n_bins;           /* N/2 + 1                                            */
+  int64_t sum_len;          /* sum_k of kept support lengths (packed table size)  */
+  int64_t l_max;            /* cap, -1 if none                                    */
+  double frame_A, frame_B;  /* min / max of P over the mask M                     */
+  double masked_fraction;   /* fraction of bins 0..N/2 outside M                  */
+  size_t workspace_bytes_per_segment;   /* max over forward / inverse / adjoints   */
+  const double* freqs;      /* [R] nominal centre frequencies (Hz)                */
+  const int32_t* centre;    /* [R] centre bins s_k                                */
+  const int32_t* half_width;/* [R] h_k                                            */
+  const int32_t* lo;        /* [R] first kept bin                                 */
+  const int32_t* hi;        /* [R] last kept bin                                  */
+  const int64_t* offset;    /* [R] start of row k in the packed tables            */
+  const double* window;     /* [sum_len] W_k on its kept bins, row after row      */
+  const double* frame;      /* [N/2+1] P                                          */
+  const uint8_t* mask;      /* [N/2+1] M                                          */
+} qtam_plan_info_t;
+
+/* Build the plan (host FP64 tables, App. A and C) and, unless
+ * QTAM_PLAN_HOST_ONLY, upload the device tables of the requested precision to
+ * the current HIP device. On failure *out is NULL.                           */
+qtam_status qtam_plan_create(const qtam_params* params, qtam_plan_t* out);
+
+/* Host pointers in *info stay valid until qtam_plan_destroy.                 */
+qtam_status qtam_plan_info(qtam_plan_t plan, qtam_plan_info_t* info);
+
+/* Frees host and device tables. Safe on NULL. The caller must make sure no
+ * enqueued work still uses the plan.                                        */
+void qtam_plan_destroy(qtam_plan_t plan);
+
+/* Workspace one call needs for `batch` segments (bytes). A smaller workspace
+ * that still holds one segment is accepted: the batch is then processed in
+ * chunks that fit.                                                           */
+size_t qtam_workspace_size(qtam_plan_t plan, int64_t batch);
+
+/* Forward transform (Sec. III; App. A): x [batch, N] real -> y [batch, R, N_out]
+ * complex. Device pointers; ws is device scratch of ws_bytes.               */
+qtam_status qtam_forward(qtam_plan_t plan, const void* x, void* y, int64_t batch,
+                         void* ws, size_t ws_bytes, qtam_stream_t stream);
+
+/* Inverse transform by the canonical dual frame (Sec. III; App. C):
+ * y [batch, R, N_out] complex -> x [batch, N] real. Any y is accepted; the
+ * result is the minimum-norm (canonical dual) synthesis restricted to M.    */
+qtam_status qtam_inverse(qtam_plan_t plan, const void* y, void* x, int64_t batch,
+                         void* ws, size_t ws_bytes, qtam_stream_t stream);
+
+/* Adjoint of qtam_forward as a real-linear map (the gradient of a real loss,
+ * App. C: the adjoint of analysis is synthesis): gy [batch, R, N_out] complex
+ * (d loss/d Re y + i d loss/d Im y) -> gx [batch, N] real.                  */
+qtam_status qtam_forward_adjoint(qtam_plan_t plan, const void* gy, void* gx, int64_t batch,
+                                 void* ws, size_t ws_bytes, qtam_stream_t stream);
+
+/* Adjoint of qtam_inverse as a real-linear map: gx [batch, N] real ->
+ * gy [batch, R, N_out] complex.                                              */
+qtam_status qtam_inverse_adjoint(qtam_plan_t plan, const void* gx, void* gy, int64_t batch,
+                                 void* ws, size_t ws_bytes, qtam_stream_t stream);
+
+/* Per-kernel timing with HIP events recorded on the call's own stream around
+ * each launch. While enabled, every launch is bracketed by two events and the
+ * durations are accumulated per kernel kind when qtam_timing_collect is
+ * called (which synchronises on those events).                              */
+qtam_status qtam_timing_enable(qtam_plan_t plan, int32_t on);
+/* Fills up to max_kinds entries: names[i] (static strings), total_ms[i] and
+ * launches[i]; returns the number of kinds in *n_kinds and resets the totals. */
+qtam_status qtam_timing_collect(qtam_plan_t plan, const char** names, double* total_ms,
+                                int64_t* launches, int32_t max_kinds, int32_t* n_kinds);
+
+const char* qtam_status_string(qtam_status status);
+
+/* Library version string, e.g. "qtam-gfx950 1.0".                           */
+const char* qtam_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTAM_H */

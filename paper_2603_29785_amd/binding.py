@@ -1,0 +1,345 @@
+"""ctypes binding of libqtam.so (include/qtam.h).
+
+Argument marshalling only: every step of the transform runs in the HIP
+kernels of the library. PyTorch provides device memory and streams. There is
+no CPU fallback: if the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("QTAM_LIB") or os.path.join(_HERE, "libqtam.so")
+
+QTAM_OK, QTAM_ERR_INVALID_ARG, QTAM_ERR_UNSUPPORTED, QTAM_ERR_WORKSPACE, QTAM_ERR_OOM, QTAM_ERR_DEVICE = range(6)
+FP32, FP64 = 0, 1
+CAP = {"cover": 0, "paper": 1, "none": 2, "manual": 3}
+NORM = {"unit_energy": 0, "paper_inv_energy": 1, "none": 2}
+WINDOW = {"bisquare": 0, "hann": 1, "kaiser": 2, "tukey": 3, "planck": 4}
+PLAN_HOST_ONLY = 1
+
+
+class QtamError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, status_string(status), status))
+
+
+class c_params(ctypes.Structure):
+    _fields_ = [
+        ("sample_rate", ctypes.c_double),
+        ("n_samples", ctypes.c_int64),
+        ("q", ctypes.c_double),
+        ("f_min", ctypes.c_double),
+        ("f_max", ctypes.c_double),
+        ("n_rows", ctypes.c_int32),
+        ("freqs", ctypes.POINTER(ctypes.c_double)),
+        ("window", ctypes.c_int32),
+        ("window_param", ctypes.c_double),
+        ("cap_mode", ctypes.c_int32),
+        ("max_window", ctypes.c_int32),
+        ("norm_mode", ctypes.c_int32),
+        ("n_out", ctypes.c_int32),
+        ("p_floor_rel", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+class c_info(ctypes.Structure):
+    _fields_ = [
+        ("n_rows", ctypes.c_int32),
+        ("n_out", ctypes.c_int32),
+        ("max_len", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("n_samples", ctypes.c_int64),
+        ("n_bins", ctypes.c_int64),
+        ("sum_len", ctypes.c_int64),
+        ("l_max", ctypes.c_int64),
+        ("frame_A", ctypes.c_double),
+        ("frame_B", ctypes.c_double),
+        ("masked_fraction", ctypes.c_double),
+        ("workspace_bytes_per_segment", ctypes.c_size_t),
+        ("freqs", ctypes.POINTER(ctypes.c_double)),
+        ("centre", ctypes.POINTER(ctypes.c_int32)),
+        ("half_width", ctypes.POINTER(ctypes.c_int32)),
+        ("lo", ctypes.POINTER(ctypes.c_int32)),
+        ("hi", ctypes.POINTER(ctypes.c_int32)),
+        ("offset", ctypes.POINTER(ctypes.c_int64)),
+        ("window", ctypes.POINTER(ctypes.c_double)),
+        ("frame", ctypes.POINTER(ctypes.c_double)),
+        ("mask", ctypes.POINTER(ctypes.c_uint8)),
+    ]
+
+
+EXPORTED = [
+    "qtam_plan_create", "qtam_plan_info", "qtam_plan_destroy", "qtam_workspace_size",
+    "qtam_forward", "qtam_inverse", "qtam_forward_adjoint", "qtam_inverse_adjoint",
+    "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string", "qtam_version",
+]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqtam.so not built at %s: run paper_2603_29785_amd.build.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    L.qtam_plan_create.argtypes = [ctypes.POINTER(c_params), ctypes.POINTER(vp)]
+    L.qtam_plan_create.restype = ctypes.c_int
+    L.qtam_plan_info.argtypes = [vp, ctypes.POINTER(c_info)]
+    L.qtam_plan_info.restype = ctypes.c_int
+    L.qtam_plan_destroy.argtypes = [vp]
+    L.qtam_plan_destroy.restype = None
+    L.qtam_workspace_size.argtypes = [vp, i64]
+    L.qtam_workspace_size.restype = sz
+    for name in ("qtam_forward", "qtam_inverse", "qtam_forward_adjoint", "qtam_inverse_adjoint"):
+        f = getattr(L, name)
+        f.argtypes = [vp, vp, vp, i64, vp, sz, vp]
+        f.restype = ctypes.c_int
+    L.qtam_timing_enable.argtypes = [vp, ctypes.c_int32]
+    L.qtam_timing_enable.restype = ctypes.c_int
+    L.qtam_timing_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32)]
+    L.qtam_timing_collect.restype = ctypes.c_int
+    L.qtam_status_string.argtypes = [ctypes.c_int]
+    L.qtam_status_string.restype = ctypes.c_char_p
+    L.qtam_version.argtypes = []
+    L.qtam_version.restype = ctypes.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def status_string(s: int) -> str:
+    return lib.qtam_status_string(int(s)).decode()
+
+
+def version() -> str:
+    return lib.qtam_version().decode()
+
+
+def _check(status: int, what: str):
+    if status != QTAM_OK:
+        raise QtamError(status, what)
+
+
+def _arr(ptr, n, dtype):
+    if n == 0:
+        return np.zeros(0, dtype=dtype)
+    return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
+
+
+@dataclass(frozen=True)
+class PlanInfo:
+    n_rows: int
+    n_out: int
+    max_len: int
+    precision: int
+    n_samples: int
+    n_bins: int
+    sum_len: int
+    l_max: int
+    frame_A: float
+    frame_B: float
+    masked_fraction: float
+    workspace_bytes_per_segment: int
+
+
+class Plan:
+    """A QTAM plan (immutable). Tables are built in FP64 on the host and
+    uploaded once to the current device unless ``host_only``."""
+
+    def __init__(self, sample_rate: float, n_samples: int, q: float, f_min: float = 0.0,
+                 f_max: float = 0.0, n_rows: int = 0, freqs=None, window: str = "bisquare",
+                 window_param: float = 0.0, cap_mode: str = "cover", max_window: int = 0,
+                 norm_mode: str = "unit_energy", n_out: int = 0, p_floor_rel: float = 1e-6,
+                 precision: str = "fp32", host_only: bool = False):
+        self._h = ctypes.c_void_p()
+        p = c_params()
+        p.sample_rate = float(sample_rate)
+        p.n_samples = int(n_samples)
+        p.q = float(q)
+        p.f_min = float(f_min)
+        p.f_max = float(f_max)
+        self._freqs = None
+        if freqs is not None:
+            self._freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+            p.freqs = self._freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            p.n_rows = int(self._freqs.size)
+        else:
+            p.n_rows = int(n_rows)
+        p.window = WINDOW[window] if isinstance(window, str) else int(window)
+        p.window_param = float(window_param)
+        p.cap_mode = CAP[cap_mode] if isinstance(cap_mode, str) else int(cap_mode)
+        p.max_window = int(max_window)
+        p.norm_mode = NORM[norm_mode] if isinstance(norm_mode, str) else int(norm_mode)
+        p.n_out = int(n_out)
+        p.p_floor_rel = float(p_floor_rel)
+        p.precision = FP64 if precision in ("fp64", FP64, "float64") else FP32
+        p.flags = PLAN_HOST_ONLY if host_only else 0
+        self.params = dict(sample_rate=sample_rate, n_samples=n_samples, q=q, f_min=f_min, f_max=f_max,
+                           n_rows=p.n_rows, window=window, window_param=window_param, cap_mode=cap_mode,
+                           max_window=max_window, norm_mode=norm_mode, n_out=n_out,
+                           p_floor_rel=p_floor_rel, precision=precision)
+        _check(lib.qtam_plan_create(ctypes.byref(p), ctypes.byref(self._h)), "qtam_plan_create")
+        ci = c_info()
+        _check(lib.qtam_plan_info(self._h, ctypes.byref(ci)), "qtam_plan_info")
+        self.info = PlanInfo(ci.n_rows, ci.n_out, ci.max_len, ci.precision, ci.n_samples, ci.n_bins,
+                             ci.sum_len, ci.l_max, ci.frame_A, ci.frame_B, ci.masked_fraction,
+                             ci.workspace_bytes_per_segment)
+        R, nb, sl = ci.n_rows, ci.n_bins, ci.sum_len
+        self.freqs = _arr(ci.freqs, R, np.float64)
+        self.centre = _arr(ci.centre, R, np.int64)
+        self.half_width = _arr(ci.half_width, R, np.int64)
+        self.lo = _arr(ci.lo, R, np.int64)
+        self.hi = _arr(ci.hi, R, np.int64)
+        self.offset = _arr(ci.offset, R, np.int64)
+        self.window_table = _arr(ci.window, sl, np.float64)
+        self.frame = _arr(ci.frame, nb, np.float64)
+        self.mask = _arr(ci.mask, nb, np.uint8).astype(bool)
+        self.host_only = host_only
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.qtam_plan_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    # ------------------------------------------------------------------ sizes
+    @property
+    def R(self) -> int:
+        return self.info.n_rows
+
+    @property
+    def N(self) -> int:
+        return self.info.n_samples
+
+    @property
+    def N_out(self) -> int:
+        return self.info.n_out
+
+    @property
+    def fp64(self) -> bool:
+        return self.info.precision == FP64
+
+    def windows_dense(self) -> np.ndarray:
+        """W as a dense [R, N/2+1] matrix (host, FP64)."""
+        W = np.zeros((self.R, self.info.n_bins))
+        for k in range(self.R):
+            a, b, o = self.lo[k], self.hi[k], self.offset[k]
+            W[k, a:b + 1] = self.window_table[o:o + b - a + 1]
+        return W
+
+    def workspace_bytes(self, batch: int) -> int:
+        return int(lib.qtam_workspace_size(self._h, int(batch)))
+
+    # ------------------------------------------------------------ transforms
+    def _torch(self):
+        import torch
+        return torch
+
+    def _real_dtype(self):
+        torch = self._torch()
+        return torch.float64 if self.fp64 else torch.float32
+
+    def _complex_dtype(self):
+        torch = self._torch()
+        return torch.complex128 if self.fp64 else torch.complex64
+
+    def _workspace(self, batch: int, device, ws=None):
+        torch = self._torch()
+        need = self.workspace_bytes(batch)
+        if ws is not None:
+            return ws
+        if self._ws is None or self._ws.numel() < need or self._ws.device != device:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=device)
+        return self._ws
+
+    def _call(self, fn, what, src, dst, batch, ws, stream):
+        torch = self._torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(src.device)
+        ws = self._workspace(batch, src.device, ws)
+        _check(fn(self._h, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), int(batch),
+                  ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size()),
+                  ctypes.c_void_p(stream.cuda_stream)), what)
+
+    def _check_signal(self, x):
+        torch = self._torch()
+        if not (isinstance(x, torch.Tensor) and x.is_cuda):
+            raise TypeError("expected a CUDA (HIP) tensor")
+        if x.dtype != self._real_dtype() or x.shape[-1] != self.N:
+            raise ValueError("expected real %s [..., %d], got %s %s" % (self._real_dtype(), self.N, x.dtype,
+                                                                        tuple(x.shape)))
+        return x.contiguous()
+
+    def _check_rows(self, y):
+        torch = self._torch()
+        if not (isinstance(y, torch.Tensor) and y.is_cuda):
+            raise TypeError("expected a CUDA (HIP) tensor")
+        if y.dtype != self._complex_dtype() or tuple(y.shape[-2:]) != (self.R, self.N_out):
+            raise ValueError("expected complex %s [..., %d, %d], got %s %s" % (
+                self._complex_dtype(), self.R, self.N_out, y.dtype, tuple(y.shape)))
+        return y.contiguous()
+
+    def forward(self, x, out=None, ws=None, stream=None):
+        """x [..., N] real -> Y [..., R, N_out] complex (Sec. III forward)."""
+        torch = self._torch()
+        x = self._check_signal(x)
+        lead = x.shape[:-1]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        y = out if out is not None else torch.empty(tuple(lead) + (self.R, self.N_out),
+                                                    dtype=self._complex_dtype(), device=x.device)
+        self._call(lib.qtam_forward, "qtam_forward", x, y, batch, ws, stream)
+        return y
+
+    def inverse(self, y, out=None, ws=None, stream=None):
+        """Y [..., R, N_out] complex -> x [..., N] real (canonical dual frame)."""
+        torch = self._torch()
+        y = self._check_rows(y)
+        lead = y.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        x = out if out is not None else torch.empty(tuple(lead) + (self.N,), dtype=self._real_dtype(),
+                                                    device=y.device)
+        self._call(lib.qtam_inverse, "qtam_inverse", y, x, batch, ws, stream)
+        return x
+
+    def forward_adjoint(self, gy, out=None, ws=None, stream=None):
+        torch = self._torch()
+        gy = self._check_rows(gy)
+        lead = gy.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        gx = out if out is not None else torch.empty(tuple(lead) + (self.N,), dtype=self._real_dtype(),
+                                                     device=gy.device)
+        self._call(lib.qtam_forward_adjoint, "qtam_forward_adjoint", gy, gx, batch, ws, stream)
+        return gx
+
+    def inverse_adjoint(self, gx, out=None, ws=None, stream=None):
+        torch = self._torch()
+        gx = self._check_signal(gx)
+        lead = gx.shape[:-1]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        gy = out if out is not None else torch.empty(tuple(lead) + (self.R, self.N_out),
+                                                     dtype=self._complex_dtype(), device=gx.device)
+        self._call(lib.qtam_inverse_adjoint, "qtam_inverse_adjoint", gx, gy, batch, ws, stream)
+        return gy
+
+    # ---------------------------------------------------------------- timing
+    def timing(self, on: bool):
+        _check(lib.qtam_timing_enable(self._h, 1 if on else 0), "qtam_timing_enable")
+
+    def timing_collect(self) -> dict:
+        n = 16
+        names = (ctypes.c_char_p * n)()
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        got = ctypes.c_int32()
+        _check(lib.qtam_timing_collect(self._h, names, ms, cnt, n, ctypes.byref(got)), "qtam_timing_collect")
+        return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(n, got.value))}

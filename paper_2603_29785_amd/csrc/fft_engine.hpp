@@ -1,0 +1,219 @@
+// Block-level Stockham FFT engine for gfx950.
+//
+// A transform of length L (a power of two) is processed by TPR = L/E threads,
+// each holding E complex values in registers. Every pass applies radix-R
+// butterflies (R = E, the last pass possibly smaller) to values held in
+// registers; between passes the values are exchanged through an LDS region of
+// the transform. First-pass inputs and last-pass outputs are addressed so that
+// consecutive threads touch consecutive elements: kernels feed the engine
+// straight from global memory and store its results straight back, coalesced.
+//
+// Layout of the registers of thread tl (tl in [0, TPR)):
+//   before the first pass: v[q*R0 + r] = a[tl + q*TPR + r*(L/R0)]
+//   after the last pass:   v[q*RL + r] = A[tl + q*TPR + r*(L/RL)]
+// Twiddles come from a table tw[m] = exp(-2 pi i m / L), m in [0, L), built on
+// the host in FP64. Direction S = -1 computes sum_n a_n e^{-2 pi i nk/L}, S = +1
+// the unnormalised inverse kernel e^{+2 pi i nk/L}.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace qtam {
+
+template <typename T> struct Complex;
+template <> struct Complex<float> { using type = float2; };
+template <> struct Complex<double> { using type = double2; };
+
+template <typename C> __device__ __forceinline__ C c_add(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C c_sub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C c_conj(C a) { return C{a.x, -a.y}; }
+template <typename C> __device__ __forceinline__ C c_mul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C, typename T> __device__ __forceinline__ C c_scale(C a, T s) { return C{a.x * s, a.y * s}; }
+// a * (S i): S = +1 multiplies by i, S = -1 by -i
+template <int S, typename C> __device__ __forceinline__ C c_mul_si(C a) {
+  if constexpr (S > 0) return C{-a.y, a.x};
+  else return C{a.y, -a.x};
+}
+
+// cos and sin of 2 pi k / 16, k = 0..4 (the rest follow by symmetry)
+struct Root16 {
+  static constexpr double c1 = 0.92387953251128675613;
+  static constexpr double s1 = 0.38268343236508977173;
+  static constexpr double r2 = 0.70710678118654752440;
+};
+
+// a * exp(S 2 pi i k / 16) for a compile-time k
+template <int S, int K, typename C>
+__device__ __forceinline__ C c_mul_root16(C a) {
+  using T = decltype(a.x);
+  constexpr int k = ((K % 16) + 16) % 16;
+  if constexpr (k == 0) return a;
+  else if constexpr (k == 4) return c_mul_si<S>(a);
+  else if constexpr (k == 8) return C{-a.x, -a.y};
+  else if constexpr (k == 12) return c_mul_si<-S>(a);
+  else if constexpr (k == 2 || k == 6 || k == 10 || k == 14) {
+    // exp(S i pi/4 * k/2) = (cx + i S sy) / sqrt 2, cx, sy in {+1, -1}
+    constexpr T r = static_cast<T>(Root16::r2);
+    constexpr T cx = (k == 2 || k == 14) ? r : -r;
+    constexpr T sy = (k == 2 || k == 6) ? static_cast<T>(S) * r : -static_cast<T>(S) * r;
+    return C{a.x * cx - a.y * sy, a.x * sy + a.y * cx};
+  } else {
+    // k odd: cos / sin of 2 pi k/16 from the first-octant values
+    constexpr int m = k % 8;                     // reduce by pi
+    constexpr T sg = k >= 8 ? T(-1) : T(1);
+    constexpr T cs = static_cast<T>(m == 1 ? Root16::c1 : m == 3 ? Root16::s1 : m == 5 ? -Root16::s1 : -Root16::c1);
+    constexpr T sn = static_cast<T>(m == 1 ? Root16::s1 : m == 3 ? Root16::c1 : m == 5 ? Root16::c1 : Root16::s1);
+    constexpr T cx = sg * cs;
+    constexpr T sy = sg * sn * static_cast<T>(S);
+    return C{a.x * cx - a.y * sy, a.x * sy + a.y * cx};
+  }
+}
+
+template <int S, typename C>
+__device__ __forceinline__ void dft2(C& a0, C& a1) {
+  const C t = a0;
+  a0 = c_add(t, a1);
+  a1 = c_sub(t, a1);
+}
+
+template <int S, typename C>
+__device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+  const C t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
+  const C t2 = c_add(a1, a3), t3 = c_mul_si<S>(c_sub(a1, a3));
+  a0 = c_add(t0, t2);
+  a2 = c_sub(t0, t2);
+  a1 = c_add(t1, t3);
+  a3 = c_sub(t1, t3);
+}
+
+// In-register DFT of R values in natural order (R in 1, 2, 4, 8, 16).
+// R = 8 and 16 split as n = 4 n1 + n2 ... : inner radix-4 DFTs over strided
+// groups, twiddles exp(S 2 pi i n2 k1 / R), outer DFTs over the groups.
+template <int S, int R, typename C>
+__device__ __forceinline__ void dft_small(C* a) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    dft2<S>(a[0], a[1]);
+  } else if constexpr (R == 4) {
+    dft4<S>(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 8) {
+    // n = 2 n1 + n2, k = k1 + 4 k2
+    dft4<S>(a[0], a[2], a[4], a[6]);
+    dft4<S>(a[1], a[3], a[5], a[7]);
+    a[3] = c_mul_root16<S, 2>(a[3]);
+    a[5] = c_mul_root16<S, 4>(a[5]);
+    a[7] = c_mul_root16<S, 6>(a[7]);
+    C y[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C e = a[2 * k1], o = a[2 * k1 + 1];
+      dft2<S>(e, o);
+      y[k1] = e;
+      y[k1 + 4] = o;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = y[i];
+  } else if constexpr (R == 16) {
+    // n = 4 n1 + n2: group n2 holds a[n2], a[4+n2], a[8+n2], a[12+n2]
+    dft4<S>(a[0], a[4], a[8], a[12]);
+    dft4<S>(a[1], a[5], a[9], a[13]);
+    dft4<S>(a[2], a[6], a[10], a[14]);
+    dft4<S>(a[3], a[7], a[11], a[15]);
+    // group n2, output k1 sits at a[4 k1 + n2]; twiddle exp(S 2 pi i n2 k1/16)
+    a[5] = c_mul_root16<S, 1>(a[5]);
+    a[9] = c_mul_root16<S, 2>(a[9]);
+    a[13] = c_mul_root16<S, 3>(a[13]);
+    a[6] = c_mul_root16<S, 2>(a[6]);
+    a[10] = c_mul_root16<S, 4>(a[10]);
+    a[14] = c_mul_root16<S, 6>(a[14]);
+    a[7] = c_mul_root16<S, 3>(a[7]);
+    a[11] = c_mul_root16<S, 6>(a[11]);
+    a[15] = c_mul_root16<S, 9>(a[15]);
+    C y[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C b0 = a[4 * k1], b1 = a[4 * k1 + 1], b2 = a[4 * k1 + 2], b3 = a[4 * k1 + 3];
+      dft4<S>(b0, b1, b2, b3);
+      y[k1] = b0;
+      y[k1 + 4] = b1;
+      y[k1 + 8] = b2;
+      y[k1 + 12] = b3;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = y[i];
+  }
+}
+
+// LDS index with one pad element every 32, which spreads power-of-two strides
+// over the banks.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
+constexpr int lds_size(int l) { return l + l / 32 + 1; }
+
+template <typename T, int L, int E, int S>
+struct BlockFft {
+  using C = typename Complex<T>::type;
+  static_assert((L & (L - 1)) == 0 && (E & (E - 1)) == 0 && E <= L && E <= 16, "pow2 sizes");
+  static constexpr int TPR = L / E;
+  static constexpr int radix(int ns) { return (L / ns >= E) ? E : L / ns; }
+  static constexpr int last_ns() {
+    int ns = 1;
+    while (ns * radix(ns) < L) ns *= radix(ns);
+    return ns;
+  }
+  static constexpr int R0 = radix(1);
+  static constexpr int RL = radix(last_ns());
+
+  __device__ static __forceinline__ int in_index(int tl, int i) {
+    return tl + (i / R0) * TPR + (i % R0) * (L / R0);
+  }
+  __device__ static __forceinline__ int out_index(int tl, int i) {
+    return tl + (i / RL) * TPR + (i % RL) * (L / RL);
+  }
+
+  template <int NS>
+  __device__ static __forceinline__ void pass(C (&v)[E], C* lds, int tl, const C* __restrict__ tw) {
+    constexpr int R = radix(NS);
+#pragma unroll
+    for (int q = 0; q < E / R; ++q) {
+      if constexpr (NS > 1) {
+        const int k = (tl + q * TPR) & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C w = tw[r * k * (L / (NS * R))];
+          if constexpr (S > 0) w.y = -w.y;
+          v[q * R + r] = c_mul(v[q * R + r], w);
+        }
+      }
+      dft_small<S, R>(&v[q * R]);
+    }
+    if constexpr (NS * R < L) {
+#pragma unroll
+      for (int q = 0; q < E / R; ++q) {
+        const int j = tl + q * TPR;
+        const int k = j & (NS - 1);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = v[q * R + r];
+      }
+      __syncthreads();
+      constexpr int R2 = radix(NS * R);
+#pragma unroll
+      for (int q = 0; q < E / R2; ++q) {
+        const int j = tl + q * TPR;
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[q * R2 + r] = lds[lds_pad(j + r * (L / R2))];
+      }
+      __syncthreads();
+      pass<NS * R>(v, lds, tl, tw);
+    }
+  }
+
+  // Every thread of the workgroup must call run (it contains barriers).
+  __device__ static __forceinline__ void run(C (&v)[E], C* lds, int tl, const C* __restrict__ tw) {
+    pass<1>(v, lds, tl, tw);
+  }
+};
+
+}  // namespace qtam

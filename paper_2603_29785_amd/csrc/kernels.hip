@@ -1,0 +1,922 @@
+// QTAM forward / inverse transform kernels for gfx950 (MI355X).
+//
+// Forward (Sec. III; App. A):
+//   1. spectrum: the N real samples of a segment, read as N/2 complex pairs
+//      z[m] = x[2m] + i x[2m+1], go through an N/2-point complex FFT
+//      (one LDS pass when N/2 fits a workgroup, else two passes of the
+//      four-step factorisation N/2 = N1 * N2 through the workspace);
+//   2. rows: one fused kernel per (segment, row) rebuilds the real-signal
+//      spectrum X[c] from the packed halves on the fly, multiplies by the
+//      window table, drops each bin at its baseband slot (c - s_k) mod N_out
+//      (roll to baseband, crop, zero pad) and runs the N_out-point inverse
+//      FFT in registers and LDS, storing the envelope row coalesced.
+// Inverse (Sec. III canonical dual; App. C):
+//   1. rows: N_out-point FFT of each envelope row; the kept slots, weighted
+//      by the dual table sqrt(N/N_out) W M / P / N, go to a packed buffer;
+//   2. overlap-add: each thread sums the covering rows of a bin pair
+//      (b, N/2-b) in fixed row order (no atomics) and applies the real-signal
+//      pre-twist, giving the N/2-point half-size spectrum;
+//   3. synthesis: N/2-point inverse FFT whose complex output, read as pairs
+//      of reals, is the time series.
+// The adjoints reuse the same kernels with other tables (App. C: the
+// adjoint of analysis is synthesis).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "fft_engine.hpp"
+#include "plan.hpp"
+#include "qtam.h"
+
+namespace qtam {
+
+// ---------------------------------------------------------------------------
+// Device-side tables
+// ---------------------------------------------------------------------------
+struct RowMeta {
+  int s, lo, hi, off;   // centre bin, kept bin range, offset in the packed tables
+};
+
+// exp(-2 pi i m / N) for m in [0, N) as fine[m & (F-1)] * coarse[m >> log2 F]
+template <typename C>
+struct Twiddle2 {
+  const C* fine;
+  const C* coarse;
+  int bits;
+  __device__ __forceinline__ C operator()(int64_t m) const {
+    const int64_t lo = m & ((int64_t(1) << bits) - 1);
+    return c_mul(fine[lo], coarse[m >> bits]);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Launch geometry
+// ---------------------------------------------------------------------------
+template <typename T> constexpr int elems_per_thread() { return sizeof(T) == 4 ? 16 : 8; }
+
+template <typename T, int L>
+struct RowGeom {
+  static constexpr int E = L < elems_per_thread<T>() ? L : elems_per_thread<T>();
+  static constexpr int TPR = L / E;
+  static constexpr int G = TPR >= 256 ? 1 : 256 / TPR;   // transforms per workgroup
+  static constexpr int NT = G * TPR;
+};
+
+// Columns per workgroup of the four-step passes: C * L values fill at most
+// 64 KiB of LDS, at least 4 columns for 32/64-byte contiguous runs.
+template <typename T, int L>
+struct ColGeom {
+  static constexpr int E = L < elems_per_thread<T>() ? L : elems_per_thread<T>();
+  static constexpr int TPR = L / E;
+  static constexpr int CAP = (65536 / (2 * int(sizeof(T)))) / L;
+  static constexpr int CC = CAP >= 16 ? 16 : (CAP >= 4 ? CAP : 4);
+  static constexpr int NT = CC * TPR;
+};
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Batched contiguous complex FFTs of length L: transform t reads
+// in[t*in_stride + n], writes out[t*out_stride + k].
+template <typename T, int L, int S>
+__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fft_rows(
+    const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
+    int64_t count, int64_t in_stride, int64_t out_stride, const typename Complex<T>::type* __restrict__ tw) {
+  using C = typename Complex<T>::type;
+  using Geo = RowGeom<T, L>;
+  using F = BlockFft<T, L, Geo::E, S>;
+  __shared__ C lds[Geo::G * lds_size(L)];
+  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
+  const int64_t tr = int64_t(blockIdx.x) * Geo::G + g;
+  const bool ok = tr < count;
+  C v[Geo::E];
+  if (ok) {
+    const C* src = in + tr * in_stride;
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) v[i] = src[F::in_index(tl, i)];
+  } else {
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) v[i] = C{0, 0};
+  }
+  F::run(v, lds + g * lds_size(L), tl, tw);
+  if (ok) {
+    C* dst = out + tr * out_stride;
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) dst[F::out_index(tl, i)] = v[i];
+  }
+}
+
+// Four-step, first pass: length-N2 FFTs down the columns n1 of the N1 x N2
+// view (element stride N1), times exp(S 2 pi i n1 k2 / M), written back in
+// place-order. CC adjacent columns per workgroup, column index fastest
+// across threads so every access is a contiguous run of CC values.
+template <typename T, int L, int S>
+__global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_cols(
+    const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
+    int64_t n1_count, int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw,
+    Twiddle2<typename Complex<T>::type> tw2) {
+  using C = typename Complex<T>::type;
+  using Geo = ColGeom<T, L>;
+  using F = BlockFft<T, L, Geo::E, S>;
+  __shared__ C lds[Geo::CC * lds_size(L)];
+  const int t = threadIdx.x, c = t % Geo::CC, tl = t / Geo::CC;
+  const int64_t n1 = int64_t(blockIdx.x) * Geo::CC + c;
+  const int64_t base = int64_t(blockIdx.y) * seg_stride + n1;
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) v[i] = in[base + n1_count * F::in_index(tl, i)];
+  F::run(v, lds + c * lds_size(L), tl, tw);
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int64_t k2 = F::out_index(tl, i);
+    C w = tw2(2 * n1 * k2);            // exp(-2 pi i n1 k2 / (N/2)) from the N-point table
+    if constexpr (S > 0) w.y = -w.y;
+    out[base + n1_count * k2] = c_mul(v[i], w);
+  }
+}
+
+// Four-step, second pass: length-N1 FFTs along the contiguous rows k2 of the
+// intermediate; CC rows per workgroup are staged through LDS with a linear
+// (coalesced) load, results go to Z[k2 + N2 k1] in runs of CC values.
+template <typename T, int L, int S>
+__global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_rows_t(
+    const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
+    int64_t n2_count, int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw) {
+  using C = typename Complex<T>::type;
+  using Geo = ColGeom<T, L>;
+  using F = BlockFft<T, L, Geo::E, S>;
+  __shared__ C lds[Geo::CC * lds_size(L)];
+  const int t = threadIdx.x;
+  const int64_t k2_0 = int64_t(blockIdx.x) * Geo::CC;
+  const C* src = in + int64_t(blockIdx.y) * seg_stride + k2_0 * L;
+  for (int i = t; i < Geo::CC * L; i += Geo::NT) lds[(i / L) * lds_size(L) + lds_pad(i % L)] = src[i];
+  __syncthreads();
+  const int c = t % Geo::CC, tl = t / Geo::CC;
+  C* reg = lds + c * lds_size(L);
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) v[i] = reg[lds_pad(F::in_index(tl, i))];
+  __syncthreads();
+  F::run(v, reg, tl, tw);
+  C* dst = out + int64_t(blockIdx.y) * seg_stride + k2_0 + c;
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) dst[n2_count * F::out_index(tl, i)] = v[i];
+}
+
+// Rebuild X[c] (c in [0, N/2]) of a real signal from the N/2-point FFT Z of
+// its even/odd pairs: X[c] = (Z[c] + Z*[N/2-c])/2 - (i/2) e^{-2 pi i c/N} (Z[c] - Z*[N/2-c]).
+template <typename C>
+__device__ __forceinline__ C real_spectrum_bin(const C* __restrict__ Z, int64_t half, int64_t c,
+                                               const Twiddle2<C>& tw2) {
+  const C zc = Z[c == half ? 0 : c];
+  const C zm = c_conj(Z[c == 0 ? 0 : half - c]);
+  const C a = c_add(zc, zm);
+  const C b = c_mul(tw2(c), c_sub(zc, zm));
+  const C x = c_add(a, c_mul_si<-1>(b));
+  return C{x.x * decltype(x.x)(0.5), x.y * decltype(x.x)(0.5)};
+}
+
+// Fused forward rows: gather + window + roll to baseband + N_out-point
+// inverse FFT + store. One transform per (segment, row).
+template <typename T, int L>
+__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
+    const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ Y,
+    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int64_t total_rows, int64_t half,
+    const typename Complex<T>::type* __restrict__ tw, Twiddle2<typename Complex<T>::type> tw2) {
+  using C = typename Complex<T>::type;
+  using Geo = RowGeom<T, L>;
+  using F = BlockFft<T, L, Geo::E, +1>;
+  __shared__ C lds[Geo::G * lds_size(L)];
+  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
+  const int64_t gr = int64_t(blockIdx.x) * Geo::G + g;
+  const bool ok = gr < total_rows;
+  const int64_t seg = ok ? gr / R : 0;
+  const RowMeta rm = rows[ok ? int(gr % R) : 0];
+  const C* Z = spec + seg * half;
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int u = F::in_index(tl, i);
+    const int j = u < L / 2 ? u : u - L;
+    const int c = rm.s + j;
+    C val{0, 0};
+    if (ok && c >= rm.lo && c <= rm.hi) {
+      const T w = tab[rm.off + (c - rm.lo)];
+      const C x = real_spectrum_bin(Z, half, int64_t(c), tw2);
+      val = C{x.x * w, x.y * w};
+    }
+    v[i] = val;
+  }
+  F::run(v, lds + g * lds_size(L), tl, tw);
+  if (ok) {
+    C* dst = Y + gr * L;
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) dst[F::out_index(tl, i)] = v[i];
+  }
+}
+
+// Inverse rows: N_out-point FFT of each envelope row, kept slots times the
+// table go to the packed per-segment buffer Sbuf[seg * sum_len + off + c - lo].
+template <typename T, int L>
+__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
+    const typename Complex<T>::type* __restrict__ Y, typename Complex<T>::type* __restrict__ Sbuf,
+    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int64_t total_rows,
+    int64_t sum_len, const typename Complex<T>::type* __restrict__ tw) {
+  using C = typename Complex<T>::type;
+  using Geo = RowGeom<T, L>;
+  using F = BlockFft<T, L, Geo::E, -1>;
+  __shared__ C lds[Geo::G * lds_size(L)];
+  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
+  const int64_t gr = int64_t(blockIdx.x) * Geo::G + g;
+  const bool ok = gr < total_rows;
+  C v[Geo::E];
+  if (ok) {
+    const C* src = Y + gr * L;
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) v[i] = src[F::in_index(tl, i)];
+  } else {
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) v[i] = C{0, 0};
+  }
+  F::run(v, lds + g * lds_size(L), tl, tw);
+  if (ok) {
+    const int64_t seg = gr / R;
+    const RowMeta rm = rows[int(gr % R)];
+    C* dst = Sbuf + seg * sum_len + rm.off - rm.lo;
+    const T* tb = tab + rm.off - rm.lo;
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) {
+      const int u = F::out_index(tl, i);
+      const int j = u < L / 2 ? u : u - L;
+      const int c = rm.s + j;
+      if (c >= rm.lo && c <= rm.hi) {
+        const T w = tb[c];
+        dst[c] = C{v[i].x * w, v[i].y * w};
+      }
+    }
+  }
+}
+
+// Overlap-add of the packed rows over the bins covered, in fixed row order,
+// followed by the pre-twist that turns the one-sided spectrum of bins p and
+// N/2-p into the half-size spectrum the synthesis FFT consumes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ola(
+    const typename Complex<T>::type* __restrict__ Sbuf, typename Complex<T>::type* __restrict__ Zout,
+    const RowMeta* __restrict__ rows, const int2* __restrict__ bins, int64_t half, int64_t sum_len,
+    Twiddle2<typename Complex<T>::type> tw2) {
+  using C = typename Complex<T>::type;
+  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p > half / 2) return;
+  const int64_t seg = blockIdx.y;
+  const C* Sseg = Sbuf + seg * sum_len;
+  auto bin_sum = [&](int64_t b) {
+    C acc{0, 0};
+    const int2 kr = bins[b];
+    for (int k = kr.x; k <= kr.y; ++k) {
+      const RowMeta rm = rows[k];
+      if (b >= rm.lo && b <= rm.hi) acc = c_add(acc, Sseg[rm.off + (b - rm.lo)]);
+    }
+    return acc;
+  };
+  const int64_t q = half - p;
+  C A = bin_sum(p);
+  C B = bin_sum(q);
+  if (p == 0) {   // DC and Nyquist: real parts only (irfft convention)
+    A.y = 0;
+    B.y = 0;
+  }
+  const C w = c_conj(tw2(p));   // exp(+2 pi i p / N)
+  const C Bc = c_conj(B), Ac = c_conj(A);
+  C* Zs = Zout + seg * half;
+  Zs[p] = c_add(c_add(A, Bc), c_mul_si<+1>(c_mul(w, c_sub(A, Bc))));
+  if (p > 0 && q != p) Zs[q] = c_add(c_add(B, Ac), c_mul_si<-1>(c_mul(c_conj(w), c_sub(B, Ac))));
+}
+
+}  // namespace qtam
+
+// ===========================================================================
+// Host side: plan object, dispatch, C ABI
+// ===========================================================================
+using namespace qtam;
+
+namespace {
+
+enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_FWD_ROWS, K_INV_ROWS, K_OLA, K_SYN, K_SYN1, K_SYN2, K_NUM };
+const char* const kKindName[K_NUM] = {"spectrum_fft", "spectrum_fft_pass1", "spectrum_fft_pass2",
+                                       "fwd_rows", "inv_rows", "overlap_add", "synthesis_fft",
+                                       "synthesis_fft_pass1", "synthesis_fft_pass2"};
+
+enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3 };
+
+constexpr int kMaxLog2Single32 = 14;   // LDS-resident FFT up to 16384 points (FP32)
+constexpr int kMaxLog2Single64 = 13;   // and 8192 points (FP64)
+
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct qtam_plan_s {
+  HostPlan hp;
+  bool device = false;
+  int device_id = -1;
+  char* dmem = nullptr;         // one allocation holding every device table
+  // device table pointers (precision of the plan)
+  RowMeta* d_rows = nullptr;
+  int2* d_bins = nullptr;
+  void* d_tab[4] = {};
+  void* d_tw_out = nullptr;     // N_out
+  void* d_tw_half = nullptr;    // N/2 (single pass) or nullptr
+  void* d_tw_n1 = nullptr;      // N1 (four-step, second pass length)
+  void* d_tw_n2 = nullptr;      // N2 (four-step, first pass length)
+  void* d_tw2_fine = nullptr;
+  void* d_tw2_coarse = nullptr;
+  int tw2_bits = 0;
+  bool four_step = false;
+  int64_t n1 = 0, n2 = 0;
+  bool gpu_supported = false;
+  qtam_status unsupported_reason = QTAM_OK;
+  size_t seg_bytes = 0;         // workspace per segment (max over operations)
+  // host info arrays
+  std::vector<int64_t> info_offset;
+  // timing
+  std::mutex mu;
+  bool timing = false;
+  struct Pending { int kind; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[K_NUM] = {};
+  int64_t launches[K_NUM] = {};
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Table construction for the device
+// ---------------------------------------------------------------------------
+template <typename T>
+void twiddles(std::vector<T>& out, int64_t L) {
+  // exp(-2 pi i m / L), interleaved, in FP64 then rounded once to T
+  out.resize(2 * L);
+  for (int64_t m = 0; m < L; ++m) {
+    const double a = -2.0 * M_PI * static_cast<double>(m) / static_cast<double>(L);
+    out[2 * m] = static_cast<T>(std::cos(a));
+    out[2 * m + 1] = static_cast<T>(std::sin(a));
+  }
+}
+
+template <typename T>
+void twiddles_strided(std::vector<T>& out, int64_t count, int64_t step, int64_t L) {
+  out.resize(2 * count);
+  for (int64_t m = 0; m < count; ++m) {
+    const double a = -2.0 * M_PI * static_cast<double>(m * step) / static_cast<double>(L);
+    out[2 * m] = static_cast<T>(std::cos(a));
+    out[2 * m + 1] = static_cast<T>(std::sin(a));
+  }
+}
+
+struct Blob {
+  std::vector<char> bytes;
+  size_t add(const void* p, size_t n) {
+    const size_t off = align256(bytes.size());
+    bytes.resize(off + n);
+    if (n) std::memcpy(bytes.data() + off, p, n);
+    return off;
+  }
+};
+
+template <typename T>
+qtam_status upload(qtam_plan_s* pl) {
+  HostPlan& hp = pl->hp;
+  Blob blob;
+  std::vector<RowMeta> rm(hp.rows);
+  for (int k = 0; k < hp.rows; ++k)
+    rm[k] = RowMeta{hp.centre[k], hp.lo[k], hp.hi[k], static_cast<int>(hp.offset[k])};
+  const size_t o_rows = blob.add(rm.data(), rm.size() * sizeof(RowMeta));
+  std::vector<int2> bins(hp.n_bins);
+  for (int64_t b = 0; b < hp.n_bins; ++b) bins[b] = int2{hp.bin_klo[b], hp.bin_khi[b]};
+  const size_t o_bins = blob.add(bins.data(), bins.size() * sizeof(int2));
+  size_t o_tab[4];
+  const std::vector<double>* src[4] = {&hp.fwd_tab, &hp.dual_tab, &hp.afwd_tab, &hp.ainv_tab};
+  for (int i = 0; i < 4; ++i) {
+    std::vector<T> v(src[i]->begin(), src[i]->end());
+    o_tab[i] = blob.add(v.data(), v.size() * sizeof(T));
+  }
+  std::vector<T> tw;
+  twiddles(tw, hp.n_out);
+  const size_t o_out = blob.add(tw.data(), tw.size() * sizeof(T));
+  size_t o_half = 0, o_n1 = 0, o_n2 = 0;
+  if (!pl->four_step) {
+    twiddles(tw, hp.half);
+    o_half = blob.add(tw.data(), tw.size() * sizeof(T));
+  } else {
+    twiddles(tw, pl->n1);
+    o_n1 = blob.add(tw.data(), tw.size() * sizeof(T));
+    twiddles(tw, pl->n2);
+    o_n2 = blob.add(tw.data(), tw.size() * sizeof(T));
+  }
+  // two-level table of exp(-2 pi i m / N)
+  const int nb = ilog2(hp.n);
+  pl->tw2_bits = (nb + 1) / 2;
+  const int64_t nfine = int64_t(1) << pl->tw2_bits, ncoarse = hp.n >> pl->tw2_bits;
+  twiddles_strided(tw, nfine, 1, hp.n);
+  const size_t o_f = blob.add(tw.data(), tw.size() * sizeof(T));
+  twiddles_strided(tw, ncoarse, nfine, hp.n);
+  const size_t o_c = blob.add(tw.data(), tw.size() * sizeof(T));
+
+  if (hipMalloc(reinterpret_cast<void**>(&pl->dmem), blob.bytes.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    pl->dmem = nullptr;
+    return QTAM_ERR_OOM;
+  }
+  if (hipMemcpy(pl->dmem, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return QTAM_ERR_DEVICE;
+  }
+  char* d = pl->dmem;
+  pl->d_rows = reinterpret_cast<RowMeta*>(d + o_rows);
+  pl->d_bins = reinterpret_cast<int2*>(d + o_bins);
+  for (int i = 0; i < 4; ++i) pl->d_tab[i] = d + o_tab[i];
+  pl->d_tw_out = d + o_out;
+  pl->d_tw_half = pl->four_step ? nullptr : d + o_half;
+  pl->d_tw_n1 = pl->four_step ? d + o_n1 : nullptr;
+  pl->d_tw_n2 = pl->four_step ? d + o_n2 : nullptr;
+  pl->d_tw2_fine = d + o_f;
+  pl->d_tw2_coarse = d + o_c;
+  return QTAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Timing hooks
+// ---------------------------------------------------------------------------
+struct Timed {
+  qtam_plan_s* pl;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(qtam_plan_s* p, int k, hipStream_t st) : pl(p), kind(k), s(st) {
+    if (!pl->timing) return;
+    std::lock_guard<std::mutex> g(pl->mu);
+    for (hipEvent_t* e : {&a, &b}) {
+      if (!pl->pool.empty()) {
+        *e = pl->pool.back();
+        pl->pool.pop_back();
+      } else if (hipEventCreate(e) != hipSuccess) {
+        *e = nullptr;
+      }
+    }
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~Timed() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(pl->mu);
+    pl->pending.push_back({kind, a, b});
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Dispatch over compile-time sizes
+// ---------------------------------------------------------------------------
+#define QTAM_POW2_CASES(X) \
+  X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+
+template <typename T, int S>
+bool launch_fft_rows(int log2l, const void* in, void* out, int64_t count, int64_t in_stride,
+                     int64_t out_stride, const void* tw, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  switch (log2l) {
+#define X(LG)                                                                                      \
+  case LG:                                                                                         \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Single32 : kMaxLog2Single64)) {               \
+      using Geo = RowGeom<T, (1 << LG)>;                                                           \
+      const int64_t blocks = (count + Geo::G - 1) / Geo::G;                                        \
+      hipLaunchKernelGGL((k_fft_rows<T, (1 << LG), S>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st, \
+                         static_cast<const C*>(in), static_cast<C*>(out), count, in_stride, out_stride, \
+                         static_cast<const C*>(tw));                                               \
+      return true;                                                                                 \
+    }                                                                                              \
+    return false;
+    QTAM_POW2_CASES(X)
+#undef X
+    default: return false;
+  }
+}
+
+#define QTAM_COL_CASES(X) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
+constexpr int kMaxLog2Col32 = 12;   // four-step sub-FFTs up to 4096 points (FP32)
+constexpr int kMaxLog2Col64 = 11;   // and 2048 points (FP64)
+
+template <typename T, int S>
+bool launch_fft_cols(int log2l, const void* in, void* out, int64_t n1, int64_t segs, int64_t seg_stride,
+                     const void* tw, Twiddle2<typename Complex<T>::type> tw2, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  switch (log2l) {
+#define X(LG)                                                                                     \
+  case LG:                                                                                        \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                     \
+      using Geo = ColGeom<T, (1 << LG)>;                                                          \
+      if (n1 % Geo::CC) return false;                                                             \
+      hipLaunchKernelGGL((k_fft_cols<T, (1 << LG), S>), dim3(unsigned(n1 / Geo::CC), unsigned(segs)), \
+                         dim3(Geo::NT), 0, st, static_cast<const C*>(in), static_cast<C*>(out), n1, \
+                         seg_stride, static_cast<const C*>(tw), tw2);                             \
+      return true;                                                                                \
+    }                                                                                             \
+    return false;
+    QTAM_COL_CASES(X)
+#undef X
+    default: return false;
+  }
+}
+
+template <typename T, int S>
+bool launch_fft_rows_t(int log2l, const void* in, void* out, int64_t n2, int64_t segs, int64_t seg_stride,
+                       const void* tw, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  switch (log2l) {
+#define X(LG)                                                                                       \
+  case LG:                                                                                          \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                       \
+      using Geo = ColGeom<T, (1 << LG)>;                                                            \
+      if (n2 % Geo::CC) return false;                                                               \
+      hipLaunchKernelGGL((k_fft_rows_t<T, (1 << LG), S>), dim3(unsigned(n2 / Geo::CC), unsigned(segs)), \
+                         dim3(Geo::NT), 0, st, static_cast<const C*>(in), static_cast<C*>(out), n2,  \
+                         seg_stride, static_cast<const C*>(tw));                                    \
+      return true;                                                                                  \
+    }                                                                                               \
+    return false;
+    QTAM_COL_CASES(X)
+#undef X
+    default: return false;
+  }
+}
+
+template <typename T>
+bool launch_rows(bool forward, int log2l, const void* in, void* out, const RowMeta* rows, const void* tab,
+                 int R, int64_t total_rows, int64_t half, int64_t sum_len, const void* tw,
+                 Twiddle2<typename Complex<T>::type> tw2, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  switch (log2l) {
+#define X(LG)                                                                                          \
+  case LG:                                                                                             \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Single32 : kMaxLog2Single64)) {                    \
+      using Geo = RowGeom<T, (1 << LG)>;                                                               \
+      const int64_t blocks = (total_rows + Geo::G - 1) / Geo::G;                                       \
+      if (forward)                                                                                     \
+        hipLaunchKernelGGL((k_fwd_rows<T, (1 << LG)>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st,   \
+                           static_cast<const C*>(in), static_cast<C*>(out), rows,                      \
+                           static_cast<const T*>(tab), R, total_rows, half, static_cast<const C*>(tw), \
+                           tw2);                                                                       \
+      else                                                                                             \
+        hipLaunchKernelGGL((k_inv_rows<T, (1 << LG)>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st,   \
+                           static_cast<const C*>(in), static_cast<C*>(out), rows,                      \
+                           static_cast<const T*>(tab), R, total_rows, sum_len,                         \
+                           static_cast<const C*>(tw));                                                 \
+      return true;                                                                                     \
+    }                                                                                                  \
+    return false;
+    QTAM_POW2_CASES(X)
+#undef X
+    default: return false;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout for a chunk of segments
+// ---------------------------------------------------------------------------
+struct WsLayout {
+  size_t spec = 0, tmp = 0, pack = 0, total = 0;
+};
+
+WsLayout layout_for(const qtam_plan_s* pl, int64_t segs) {
+  const size_t cb = (pl->hp.precision == QTAM_FP64 ? 16 : 8);
+  WsLayout w;
+  size_t off = 0;
+  w.spec = off;
+  off = align256(off + size_t(segs) * size_t(pl->hp.half) * cb);
+  w.tmp = off;
+  if (pl->four_step) off = align256(off + size_t(segs) * size_t(pl->hp.half) * cb);
+  w.pack = off;
+  off = align256(off + size_t(segs) * size_t(pl->hp.sum_len) * cb);
+  w.total = off;
+  return w;
+}
+
+int64_t chunk_for(const qtam_plan_s* pl, int64_t batch, size_t ws_bytes) {
+  if (layout_for(pl, 1).total > ws_bytes) return 0;
+  int64_t lo = 1, hi = batch;
+  while (lo < hi) {   // largest chunk whose layout fits
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (layout_for(pl, mid).total <= ws_bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// The two halves of the path, for one chunk
+// ---------------------------------------------------------------------------
+template <typename T>
+Twiddle2<typename Complex<T>::type> tw2_of(const qtam_plan_s* pl) {
+  using C = typename Complex<T>::type;
+  return Twiddle2<C>{static_cast<const C*>(pl->d_tw2_fine), static_cast<const C*>(pl->d_tw2_coarse),
+                     pl->tw2_bits};
+}
+
+// analysis: real signal x -> rows (forward with T_FWD, inverse adjoint with T_AINV)
+template <typename T>
+bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t segs, char* ws,
+                  const WsLayout& lay, hipStream_t st) {
+  const HostPlan& hp = pl->hp;
+  const int64_t half = hp.half;
+  void* spec = ws + lay.spec;
+  bool ok;
+  if (!pl->four_step) {
+    Timed tm(pl, K_SPEC, st);
+    ok = launch_fft_rows<T, -1>(ilog2(half), x, spec, segs, half, half, pl->d_tw_half, st);
+  } else {
+    void* tmp = ws + lay.tmp;
+    {
+      Timed tm(pl, K_SPEC1, st);
+      ok = launch_fft_cols<T, -1>(ilog2(pl->n2), x, tmp, pl->n1, segs, half, pl->d_tw_n2, tw2_of<T>(pl), st);
+    }
+    if (ok) {
+      Timed tm(pl, K_SPEC2, st);
+      ok = launch_fft_rows_t<T, -1>(ilog2(pl->n1), tmp, spec, pl->n2, segs, half, pl->d_tw_n1, st);
+    }
+  }
+  if (!ok) return false;
+  Timed tm(pl, K_FWD_ROWS, st);
+  return launch_rows<T>(true, ilog2(hp.n_out), spec, y, pl->d_rows, pl->d_tab[table], hp.rows,
+                        segs * hp.rows, half, hp.sum_len, pl->d_tw_out, tw2_of<T>(pl), st);
+}
+
+// synthesis: rows -> real signal (inverse with T_DUAL, forward adjoint with T_AFWD)
+template <typename T>
+bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t segs, char* ws,
+                   const WsLayout& lay, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  const HostPlan& hp = pl->hp;
+  const int64_t half = hp.half;
+  void* spec = ws + lay.spec;
+  void* pack = ws + lay.pack;
+  bool ok;
+  {
+    Timed tm(pl, K_INV_ROWS, st);
+    ok = launch_rows<T>(false, ilog2(hp.n_out), y, pack, pl->d_rows, pl->d_tab[table], hp.rows,
+                        segs * hp.rows, half, hp.sum_len, pl->d_tw_out, tw2_of<T>(pl), st);
+  }
+  if (!ok) return false;
+  {
+    Timed tm(pl, K_OLA, st);
+    const int64_t pairs = half / 2 + 1;
+    hipLaunchKernelGGL((k_ola<T>), dim3(unsigned((pairs + 255) / 256), unsigned(segs)), dim3(256), 0, st,
+                       static_cast<const C*>(pack), static_cast<C*>(spec), pl->d_rows, pl->d_bins, half,
+                       hp.sum_len, tw2_of<T>(pl));
+  }
+  if (!pl->four_step) {
+    Timed tm(pl, K_SYN, st);
+    return launch_fft_rows<T, +1>(ilog2(half), spec, x, segs, half, half, pl->d_tw_half, st);
+  }
+  void* tmp = ws + lay.tmp;
+  {
+    Timed tm(pl, K_SYN1, st);
+    ok = launch_fft_cols<T, +1>(ilog2(pl->n2), spec, tmp, pl->n1, segs, half, pl->d_tw_n2, tw2_of<T>(pl), st);
+  }
+  if (!ok) return false;
+  Timed tm(pl, K_SYN2, st);
+  return launch_fft_rows_t<T, +1>(ilog2(pl->n1), tmp, x, pl->n2, segs, half, pl->d_tw_n1, st);
+}
+
+enum Op { OP_FORWARD, OP_INVERSE, OP_FWD_ADJ, OP_INV_ADJ };
+
+qtam_status run_op(qtam_plan_t pl, Op op, const void* in, void* out, int64_t batch, void* ws, size_t ws_bytes,
+                   qtam_stream_t stream) {
+  if (!pl || batch < 0) return QTAM_ERR_INVALID_ARG;
+  if (batch == 0) return QTAM_OK;
+  if (!in || !out || !ws) return QTAM_ERR_INVALID_ARG;
+  if (!pl->gpu_supported) return pl->unsupported_reason;
+  if (!pl->device) return QTAM_ERR_INVALID_ARG;
+  const int64_t chunk = std::min<int64_t>(chunk_for(pl, batch, ws_bytes), 65535);
+  if (chunk < 1) return QTAM_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const HostPlan& hp = pl->hp;
+  const bool f64 = hp.precision == QTAM_FP64;
+  const size_t rb = f64 ? 8 : 4;
+  const size_t x_seg = size_t(hp.n) * rb;
+  const size_t y_seg = size_t(hp.rows) * size_t(hp.n_out) * 2 * rb;
+  const bool analysis = (op == OP_FORWARD || op == OP_INV_ADJ);
+  const int table = op == OP_FORWARD ? T_FWD : op == OP_INVERSE ? T_DUAL : op == OP_FWD_ADJ ? T_AFWD : T_AINV;
+  (void)hipGetLastError();
+  for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+    const int64_t segs = std::min(chunk, batch - b0);
+    const WsLayout lay = layout_for(pl, segs);
+    const char* src = static_cast<const char*>(in) + size_t(b0) * (analysis ? x_seg : y_seg);
+    char* dst = static_cast<char*>(out) + size_t(b0) * (analysis ? y_seg : x_seg);
+    bool ok;
+    if (analysis)
+      ok = f64 ? run_analysis<double>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st)
+               : run_analysis<float>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st);
+    else
+      ok = f64 ? run_synthesis<double>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st)
+               : run_synthesis<float>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st);
+    if (!ok) return QTAM_ERR_UNSUPPORTED;
+    if (hipGetLastError() != hipSuccess) return QTAM_ERR_DEVICE;
+  }
+  return QTAM_OK;
+}
+
+// Which sizes the kernels cover; sets the four-step split of N/2.
+void choose_geometry(qtam_plan_s* pl) {
+  const HostPlan& hp = pl->hp;
+  const bool f64 = hp.precision == QTAM_FP64;
+  const int max_single = f64 ? kMaxLog2Single64 : kMaxLog2Single32;
+  pl->gpu_supported = false;
+  pl->unsupported_reason = QTAM_ERR_UNSUPPORTED;
+  if (!is_pow2(hp.n) || !is_pow2(hp.n_out)) return;
+  const int ln = ilog2(hp.n_out);
+  if (ln < 2 || ln > max_single) return;
+  const int lh = ilog2(hp.half);
+  if (lh < 3) return;
+  if (lh <= std::min(max_single, 13)) {
+    pl->four_step = false;
+  } else {
+    pl->four_step = true;
+    const int l2 = lh / 2, l1 = lh - l2;   // N/2 = N1 * N2, N1 >= N2
+    pl->n1 = int64_t(1) << l1;
+    pl->n2 = int64_t(1) << l2;
+    if (l1 > (f64 ? kMaxLog2Col64 : kMaxLog2Col32) || l2 < 3) return;
+  }
+  pl->gpu_supported = true;
+  pl->unsupported_reason = QTAM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* qtam_version(void) { return "qtam-gfx950 1.0"; }
+
+const char* qtam_status_string(qtam_status s) {
+  switch (s) {
+    case QTAM_OK: return "ok";
+    case QTAM_ERR_INVALID_ARG: return "invalid argument";
+    case QTAM_ERR_UNSUPPORTED: return "unsupported on this device path";
+    case QTAM_ERR_WORKSPACE: return "workspace too small";
+    case QTAM_ERR_OOM: return "device out of memory";
+    case QTAM_ERR_DEVICE: return "HIP device error";
+  }
+  return "unknown status";
+}
+
+qtam_status qtam_plan_create(const qtam_params* params, qtam_plan_t* out) {
+  if (!out) return QTAM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!params) return QTAM_ERR_INVALID_ARG;
+  qtam_plan_s* pl = new (std::nothrow) qtam_plan_s();
+  if (!pl) return QTAM_ERR_OOM;
+  qtam_status st = build_host_plan(*params, pl->hp);
+  if (st != QTAM_OK) {
+    delete pl;
+    return st;
+  }
+  choose_geometry(pl);
+  pl->seg_bytes = layout_for(pl, 1).total;
+  if (!(params->flags & QTAM_PLAN_HOST_ONLY) && pl->gpu_supported) {
+    if (hipGetDevice(&pl->device_id) != hipSuccess) {
+      (void)hipGetLastError();
+      delete pl;
+      return QTAM_ERR_DEVICE;
+    }
+    st = pl->hp.precision == QTAM_FP64 ? upload<double>(pl) : upload<float>(pl);
+    if (st != QTAM_OK) {
+      if (pl->dmem) (void)hipFree(pl->dmem);
+      delete pl;
+      return st;
+    }
+    pl->device = true;
+  }
+  *out = pl;
+  return QTAM_OK;
+}
+
+qtam_status qtam_plan_info(qtam_plan_t pl, qtam_plan_info_t* info) {
+  if (!pl || !info) return QTAM_ERR_INVALID_ARG;
+  const HostPlan& hp = pl->hp;
+  info->n_rows = hp.rows;
+  info->n_out = hp.n_out;
+  info->max_len = hp.max_len;
+  info->precision = hp.precision;
+  info->n_samples = hp.n;
+  info->n_bins = hp.n_bins;
+  info->sum_len = hp.sum_len;
+  info->l_max = hp.l_max;
+  info->frame_A = hp.frame_A;
+  info->frame_B = hp.frame_B;
+  info->masked_fraction = hp.masked_fraction;
+  info->workspace_bytes_per_segment = pl->seg_bytes;
+  info->freqs = hp.freq.data();
+  info->centre = hp.centre.data();
+  info->half_width = hp.half_width.data();
+  info->lo = hp.lo.data();
+  info->hi = hp.hi.data();
+  info->offset = hp.offset.data();
+  info->window = hp.win.data();
+  info->frame = hp.P.data();
+  info->mask = hp.M.data();
+  return QTAM_OK;
+}
+
+void qtam_plan_destroy(qtam_plan_t pl) {
+  if (!pl) return;
+  for (auto& p : pl->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : pl->pool) (void)hipEventDestroy(e);
+  if (pl->dmem) (void)hipFree(pl->dmem);
+  delete pl;
+}
+
+size_t qtam_workspace_size(qtam_plan_t pl, int64_t batch) {
+  if (!pl || batch < 1) return 0;
+  return layout_for(pl, batch).total;
+}
+
+qtam_status qtam_forward(qtam_plan_t pl, const void* x, void* y, int64_t batch, void* ws, size_t ws_bytes,
+                         qtam_stream_t stream) {
+  return run_op(pl, OP_FORWARD, x, y, batch, ws, ws_bytes, stream);
+}
+
+qtam_status qtam_inverse(qtam_plan_t pl, const void* y, void* x, int64_t batch, void* ws, size_t ws_bytes,
+                         qtam_stream_t stream) {
+  return run_op(pl, OP_INVERSE, y, x, batch, ws, ws_bytes, stream);
+}
+
+qtam_status qtam_forward_adjoint(qtam_plan_t pl, const void* gy, void* gx, int64_t batch, void* ws,
+                                 size_t ws_bytes, qtam_stream_t stream) {
+  return run_op(pl, OP_FWD_ADJ, gy, gx, batch, ws, ws_bytes, stream);
+}
+
+qtam_status qtam_inverse_adjoint(qtam_plan_t pl, const void* gx, void* gy, int64_t batch, void* ws,
+                                 size_t ws_bytes, qtam_stream_t stream) {
+  return run_op(pl, OP_INV_ADJ, gx, gy, batch, ws, ws_bytes, stream);
+}
+
+qtam_status qtam_timing_enable(qtam_plan_t pl, int32_t on) {
+  if (!pl) return QTAM_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(pl->mu);
+  pl->timing = on != 0;
+  return QTAM_OK;
+}
+
+qtam_status qtam_timing_collect(qtam_plan_t pl, const char** names, double* total_ms, int64_t* launches,
+                                int32_t max_kinds, int32_t* n_kinds) {
+  if (!pl) return QTAM_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> g(pl->mu);
+  qtam_status st = QTAM_OK;
+  for (auto& p : pl->pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) {
+      (void)hipGetLastError();
+      st = QTAM_ERR_DEVICE;
+    } else {
+      pl->total_ms[p.kind] += ms;
+      pl->launches[p.kind] += 1;
+    }
+    pl->pool.push_back(p.a);
+    pl->pool.push_back(p.b);
+  }
+  pl->pending.clear();
+  int32_t n = 0;
+  for (int k = 0; k < K_NUM; ++k) {
+    if (pl->launches[k] == 0) continue;
+    if (n < max_kinds) {
+      if (names) names[n] = kKindName[k];
+      if (total_ms) total_ms[n] = pl->total_ms[k];
+      if (launches) launches[n] = pl->launches[k];
+    }
+    ++n;
+    pl->total_ms[k] = 0.0;
+    pl->launches[k] = 0;
+  }
+  if (n_kinds) *n_kinds = n;
+  return st;
+}
+
+}  // extern "C"

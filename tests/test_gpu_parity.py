@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle,
+element by element on the same seeded inputs.
+
+Bars (rel-L2 per segment): FP32 <= 1e-5, FP64 <= 1e-12, on coefficients and on
+reconstruction, for plans without frame holes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import oracle as o
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "fp64": 1e-12}
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def rel_rows(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def plans(fs, n, q, f_min, f_max, rows, precision, **kw):
+    import paper_2603_29785_amd as qt
+    gp = qt.Plan(fs, n, q, f_min, f_max, rows, precision=precision, **kw)
+    ckw = dict(cap_mode=o.CAP_COVER)
+    if "cap_mode" in kw:
+        ckw["cap_mode"] = {"cover": 0, "paper": 1, "none": 2, "manual": 3}[kw["cap_mode"]]
+    for k in ("n_out", "p_floor_rel", "max_window"):
+        if k in kw:
+            ckw[k] = kw[k]
+    op = o.OraclePlan(fs=fs, n=n, q=q, f_min=f_min, f_max=f_max, rows=rows, **ckw)
+    assert gp.N_out == op.N_out and gp.R == op.R
+    return gp, op
+
+
+def to_dev(torch, a, precision):
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt, device="cuda")
+
+
+def host_input(x, precision):
+    return x.astype(np.float32).astype(np.float64) if precision == "fp32" else x.astype(np.float64)
+
+
+CASES = [
+    # (fs, N, Q, f_min, f_max, R, batch) spanning single-pass and four-step
+    # spectra, small to large N_out, ragged batches
+    (4096.0, 16384, 8.0, 20.0, 1000.0, 64, 3),      # the one-segment workload plan (N_out 512)
+    (1024.0, 1024, 4.0, 8.0, 400.0, 12, 5),         # tiny: N/2 = 512, N_out 64
+    (256.0, 256, 2.0, 4.0, 128.0, 7, 9),            # band reaches Nyquist
+    (4096.0, 32768, 8.0, 20.0, 2000.0, 128, 2),     # differentiable-workload plan, four-step spectrum
+    (2048.0, 65536, 16.0, 10.0, 1024.0, 40, 2),     # N_out 8192 / 4096
+    (4096.0, 131072, 4.0, 10.0, 2048.0, 256, 1),    # batched-workload plan, N_out 4096
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", CASES, ids=[f"N{c[1]}_R{c[5]}_Q{int(c[2])}" for c in CASES])
+def test_forward_inverse_parity(torch_dev, case, precision):
+    torch = torch_dev
+    fs, n, q, fmin, fmax, R, B = case
+    gp, op = plans(fs, n, q, fmin, fmax, R, precision)
+    print(f"case N={n} R={R} Q={q} N_out={gp.N_out} B={B} {precision}", flush=True)
+    x = np.stack([synthetic.injected_segment(n, fs, synthetic.rng_for(9, i))[0] for i in range(B)])
+    xh = host_input(x, precision)
+    Y_ref = op.forward(xh)
+    Y = gp.forward(to_dev(torch, xh, precision)).cpu().numpy()
+    assert Y.shape == Y_ref.shape
+    err = rel_rows(Y, Y_ref)
+    print("forward rel-L2", err.max(), flush=True)
+    assert err.max() <= TOL[precision]
+    # inverse of the oracle's coefficients (cast to the device precision)
+    Yc = Y_ref.astype(np.complex64).astype(np.complex128) if precision == "fp32" else Y_ref
+    x_ref = op.inverse(Yc)
+    ydev = torch.from_numpy(Yc).to(torch.complex64 if precision == "fp32" else torch.complex128).cuda()
+    xr = gp.inverse(ydev).cpu().numpy()
+    err = rel_rows(xr, x_ref)
+    print("inverse rel-L2", err.max(), flush=True)
+    assert err.max() <= TOL[precision]
+    # round trip through the GPU vs the projection x_M
+    xm = op.project(xh)
+    rt = gp.inverse(gp.forward(to_dev(torch, xh, precision))).cpu().numpy()
+    err = rel_rows(rt, xm)
+    print("round-trip rel-L2", err.max(), flush=True)
+    assert err.max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_single_segment_workload(torch_dev, precision):
+    """4 s of white noise + sine-Gaussian, Q = 8, 64 rows 20-1000 Hz."""
+    torch = torch_dev
+    gp, op = plans(4096.0, 16384, 8.0, 20.0, 1000.0, 64, precision)
+    x = host_input(synthetic.single_segment(), precision)
+    Y = gp.forward(to_dev(torch, x, precision)).cpu().numpy()
+    assert rel(Y, op.forward(x)) <= TOL[precision]
+    # a sine-Gaussian at 100 Hz peaks in the row containing 100 Hz
+    k = int(np.argmax(np.abs(Y).max(axis=1)))
+    f = gp.freqs
+    assert f[max(k - 2, 0)] <= 100.0 <= f[min(k + 2, len(f) - 1)]
+    xr = gp.inverse(torch.from_numpy(Y).cuda()).cpu().numpy()
+    assert rel(xr, op.project(x)) <= TOL[precision]
+
+
+def test_paper_cap_plan_parity(torch_dev):
+    """The literal App. A cap (frame holes masked out)."""
+    torch = torch_dev
+    gp, op = plans(4096.0, 16384, 8.0, 20.0, 1000.0, 64, "fp64", cap_mode="paper")
+    x = np.random.default_rng(4).standard_normal((2, 16384))
+    Y = gp.forward(to_dev(torch, x, "fp64")).cpu().numpy()
+    assert rel(Y, op.forward(x)) <= 1e-12
+    xr = gp.inverse(torch.from_numpy(Y).cuda()).cpu().numpy()
+    assert rel(xr, op.inverse(op.forward(x))) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batched_workload_sampled(torch_dev, precision):
+    """256 segments x 131072 samples at the benchmark's launch configuration;
+    sampled segments against the oracle, every segment against invariants."""
+    torch = torch_dev
+    B = 256 if precision == "fp32" else 32
+    gp, op = plans(4096.0, 131072, 8.0, 10.0, 2048.0, 256, precision)
+    x = synthetic.batched_segments(B, dtype=np.float64)
+    xh = host_input(x, precision)
+    xd = to_dev(torch, xh, precision)
+    Y = gp.forward(xd)
+    xr = gp.inverse(Y)
+    for i in (0, B // 2 + 3, B - 1):
+        Yr = op.forward(xh[i])
+        assert rel(Y[i].cpu().numpy(), Yr) <= TOL[precision], i
+        assert rel(xr[i].cpu().numpy(), op.project(xh[i])) <= TOL[precision], i
+    # every segment: round trip leaves only the out-of-mask part; the
+    # energy of each row equals the energy of its dense tile (Parseval)
+    Xd = torch.fft.rfft(xd.double(), dim=-1)
+    Mk = torch.from_numpy(gp.mask).cuda()
+    xm = torch.fft.irfft(Xd * Mk, n=131072, dim=-1)
+    e = torch.linalg.norm(xr.double() - xm, dim=-1) / torch.linalg.norm(xm, dim=-1)
+    assert float(e.max()) <= TOL[precision]
+
+
+def test_linearity_and_determinism(torch_dev):
+    torch = torch_dev
+    gp, _ = plans(4096.0, 32768, 8.0, 20.0, 2000.0, 128, "fp32")
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x1 = torch.randn(4, 32768, device="cuda", generator=g)
+    x2 = torch.randn(4, 32768, device="cuda", generator=g)
+    a, b = 0.75, -1.25
+    lhs = gp.forward(a * x1 + b * x2)
+    rhs = a * gp.forward(x1) + b * gp.forward(x2)
+    assert float(torch.linalg.norm(lhs - rhs) / torch.linalg.norm(rhs)) < 1e-5
+    y1 = gp.forward(x1)
+    y2 = gp.forward(x1)
+    assert torch.equal(y1, y2)
+    # a segment alone and inside a batch gives the same bits
+    alone = gp.forward(x1[2:3].contiguous())
+    assert torch.equal(alone[0], y1[2])
+    inv_all = gp.inverse(y1)
+    inv_one = gp.inverse(y1[1:2].contiguous())
+    assert torch.equal(inv_one[0], inv_all[1])
+
+
+def test_chunked_workspace_matches(torch_dev):
+    torch = torch_dev
+    gp, _ = plans(4096.0, 65536, 8.0, 10.0, 2048.0, 96, "fp32")
+    x = torch.randn(7, 65536, device="cuda")
+    full = gp.forward(x)
+    one = gp.workspace_bytes(1)
+    ws = torch.empty(one * 2 + 10, dtype=torch.uint8, device="cuda")   # two segments per chunk
+    part = gp.forward(x, ws=ws)
+    assert torch.equal(full, part)
+    xi_full = gp.inverse(full)
+    xi_part = gp.inverse(full, ws=ws)
+    assert torch.equal(xi_full, xi_part)
+
+
+def test_errors_and_empty(torch_dev):
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    gp, _ = plans(1024.0, 4096, 8.0, 10.0, 400.0, 16, "fp32")
+    x = torch.zeros(0, 4096, device="cuda")
+    y = gp.forward(x)
+    assert y.shape == (0, 16, gp.N_out)
+    tiny = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(qt.QtamError) as e:
+        gp.forward(torch.zeros(2, 4096, device="cuda"), ws=tiny)
+    assert e.value.status == 3
+    # non power-of-two segment length is not on the GPU path
+    bad = qt.Plan(4096.0, 24576, 8.0, 20.0, 1000.0, 62)
+    with pytest.raises(qt.QtamError) as e:
+        bad.forward(torch.zeros(1, 24576, device="cuda"))
+    assert e.value.status == 2
