@@ -11,12 +11,21 @@
 // Layout of the registers of thread tl (tl in [0, TPR)):
 //   before the first pass: v[q*R0 + r] = a[tl + q*TPR + r*(L/R0)]
 //   after the last pass:   v[q*RL + r] = A[tl + q*TPR + r*(L/RL)]
-// Twiddles come from a table tw[m] = exp(-2 pi i m / L), m in [0, L), built on
-// the host in FP64. Direction S = -1 computes sum_n a_n e^{-2 pi i nk/L}, S = +1
-// the unnormalised inverse kernel e^{+2 pi i nk/L}.
+// Twiddles: every pass after the first (stride NS, radix R) needs
+// w^r, w = exp(-2 pi i k / (NS R)), r in [1, R), for its k = j mod NS. A
+// per-pass table built on the host in FP64 holds only the base powers
+// w^1, w^2, w^4, w^8 (those below R) in blocks [s*NS + k], so the threads of a
+// wave, which hold consecutive k, read consecutive entries; the other powers
+// are products of at most three of them. Four loads instead of fifteen per
+// radix-16 pass keep the twiddle traffic small next to the data streamed
+// through the caches. Direction S = -1 computes sum_n a_n e^{-2 pi i nk/L},
+// S = +1 the unnormalised inverse kernel e^{+2 pi i nk/L} (conjugated
+// twiddles).
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "gmem.hpp"
 
 namespace qtam {
 
@@ -151,7 +160,9 @@ __device__ __forceinline__ void dft_small(C* a) {
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
 constexpr int lds_size(int l) { return l + l / 32 + 1; }
 
-template <typename T, int L, int E, int S>
+// PREFETCH: request the twiddles of the next pass before the LDS exchange
+// (more registers live across the barrier) instead of after it.
+template <typename T, int L, int E, int S, bool PREFETCH = false>
 struct BlockFft {
   using C = typename Complex<T>::type;
   static_assert((L & (L - 1)) == 0 && (E & (E - 1)) == 0 && E <= L && E <= 16, "pow2 sizes");
@@ -164,6 +175,18 @@ struct BlockFft {
   }
   static constexpr int R0 = radix(1);
   static constexpr int RL = radix(last_ns());
+  // number of stored base powers w^(2^s) < R of a radix-R pass
+  static constexpr int slots(int r) { return r >= 16 ? 4 : r >= 8 ? 3 : r >= 4 ? 2 : r >= 2 ? 1 : 0; }
+  // start of the twiddle block of the pass with stride ns
+  static constexpr int tw_offset(int ns) {
+    int off = 0, n = 1;
+    while (n < ns) {
+      if (n > 1) off += slots(radix(n)) * n;
+      n *= radix(n);
+    }
+    return off;
+  }
+  static constexpr int tw_size() { return tw_offset(L); }
 
   __device__ static __forceinline__ int in_index(int tl, int i) {
     return tl + (i / R0) * TPR + (i % R0) * (L / R0);
@@ -172,23 +195,56 @@ struct BlockFft {
     return tl + (i / RL) * TPR + (i % RL) * (L / RL);
   }
 
+  // Twiddles of the pass with stride NS for this thread: w[q*R + r], r >= 1,
+  // from the base powers w^1, w^2, w^4, w^8.
   template <int NS>
-  __device__ static __forceinline__ void pass(C (&v)[E], C* lds, int tl, const C* __restrict__ tw) {
+  __device__ static __forceinline__ void load_twiddles(C (&w)[E], int tl, rsrc_t tw) {
     constexpr int R = radix(NS);
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
+      const uint32_t k = static_cast<uint32_t>((tl + q * TPR) & (NS - 1));
+      C a[16];
+#pragma unroll
+      for (int sl = 0; sl < slots(R); ++sl)
+        a[1 << sl] = bload<C>(tw, k * sizeof(C), (tw_offset(NS) + sl * NS) * sizeof(C));
+      if constexpr (R > 2) a[3] = c_mul(a[2], a[1]);
+      if constexpr (R > 4) {
+        a[5] = c_mul(a[4], a[1]);
+        a[6] = c_mul(a[4], a[2]);
+        a[7] = c_mul(a[4], a[3]);
+      }
+      if constexpr (R > 8) {
+#pragma unroll
+        for (int r = 9; r < 16; ++r) a[r] = c_mul(a[8], a[r - 8]);
+      }
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[q * R + r] = a[r];
+    }
+  }
+
+  // One radix-R pass on registers (twiddles w already loaded for NS > 1),
+  // then, unless it was the last, the next pass's twiddles are requested and
+  // the values exchanged through LDS while they arrive.
+  template <int NS>
+  __device__ static __forceinline__ void pass(C (&v)[E], C (&w)[E], C* lds, int tl, rsrc_t tw) {
+    constexpr int R = radix(NS);
+    if constexpr (!PREFETCH && NS > 1) load_twiddles<NS>(w, tl, tw);
+#pragma unroll
+    for (int q = 0; q < E / R; ++q) {
       if constexpr (NS > 1) {
-        const int k = (tl + q * TPR) & (NS - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C w = tw[r * k * (L / (NS * R))];
-          if constexpr (S > 0) w.y = -w.y;
-          v[q * R + r] = c_mul(v[q * R + r], w);
+          C t = w[q * R + r];
+          if constexpr (S > 0) t.y = -t.y;
+          v[q * R + r] = c_mul(v[q * R + r], t);
         }
       }
       dft_small<S, R>(&v[q * R]);
     }
     if constexpr (NS * R < L) {
+      constexpr int NS2 = NS * R;
+      constexpr int R2 = radix(NS2);
+      if constexpr (PREFETCH) load_twiddles<NS2>(w, tl, tw);
 #pragma unroll
       for (int q = 0; q < E / R; ++q) {
         const int j = tl + q * TPR;
@@ -198,7 +254,6 @@ struct BlockFft {
         for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = v[q * R + r];
       }
       __syncthreads();
-      constexpr int R2 = radix(NS * R);
 #pragma unroll
       for (int q = 0; q < E / R2; ++q) {
         const int j = tl + q * TPR;
@@ -206,13 +261,21 @@ struct BlockFft {
         for (int r = 0; r < R2; ++r) v[q * R2 + r] = lds[lds_pad(j + r * (L / R2))];
       }
       __syncthreads();
-      pass<NS * R>(v, lds, tl, tw);
+      pass<NS2>(v, w, lds, tl, tw);
     }
   }
 
   // Every thread of the workgroup must call run (it contains barriers).
-  __device__ static __forceinline__ void run(C (&v)[E], C* lds, int tl, const C* __restrict__ tw) {
-    pass<1>(v, lds, tl, tw);
+  // tw: buffer resource over the per-pass twiddle table of this (L, E).
+  __device__ static __forceinline__ void run(C (&v)[E], C* lds, int tl, rsrc_t tw) {
+    C w[E];
+    pass<1>(v, w, lds, tl, tw);
+  }
+  // offsets of register element i from the thread's own index tl
+  static constexpr int in_off(int i) { return (i / R0) * TPR + (i % R0) * (L / R0); }
+  static constexpr int out_off(int i) { return (i / RL) * TPR + (i % RL) * (L / RL); }
+  __device__ static __forceinline__ rsrc_t twiddles(const C* tw) {
+    return make_rsrc(tw, static_cast<uint32_t>((tw_size() > 0 ? tw_size() : 1) * sizeof(C)));
   }
 };
 

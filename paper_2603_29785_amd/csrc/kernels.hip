@@ -83,32 +83,31 @@ struct ColGeom {
 // ---------------------------------------------------------------------------
 
 // Batched contiguous complex FFTs of length L: transform t reads
-// in[t*in_stride + n], writes out[t*out_stride + k].
+// in[t*stride + n] and writes out[t*stride + k]. A chunk holds count
+// transforms; every buffer of it is below 2 GiB.
 template <typename T, int L, int S>
 __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fft_rows(
     const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
-    int64_t count, int64_t in_stride, int64_t out_stride, const typename Complex<T>::type* __restrict__ tw) {
+    int64_t count, int64_t stride, const typename Complex<T>::type* __restrict__ tw) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, S>;
   __shared__ C lds[Geo::G * lds_size(L)];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
-  const int64_t tr = int64_t(blockIdx.x) * Geo::G + g;
-  const bool ok = tr < count;
+  const int64_t tr0 = int64_t(blockIdx.x) * Geo::G;
+  const int64_t nt = count - tr0 < Geo::G ? count - tr0 : Geo::G;   // transforms of this block
+  const uint32_t bytes = static_cast<uint32_t>((nt - 1) * stride + L) * sizeof(C);
+  // lanes of transforms past the end fall outside [0, bytes): loads give 0
+  const rsrc_t rin = make_rsrc(in + tr0 * stride, bytes);
+  const rsrc_t rout = make_rsrc(out + tr0 * stride, bytes);
+  const uint32_t vb = static_cast<uint32_t>(g * stride + tl) * sizeof(C);
   C v[Geo::E];
-  if (ok) {
-    const C* src = in + tr * in_stride;
 #pragma unroll
-    for (int i = 0; i < Geo::E; ++i) v[i] = src[F::in_index(tl, i)];
-  } else {
+  for (int i = 0; i < Geo::E; ++i) v[i] = bload<C>(rin, vb, F::in_off(i) * sizeof(C));
+  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+  if (g < nt) {
 #pragma unroll
-    for (int i = 0; i < Geo::E; ++i) v[i] = C{0, 0};
-  }
-  F::run(v, lds + g * lds_size(L), tl, tw);
-  if (ok) {
-    C* dst = out + tr * out_stride;
-#pragma unroll
-    for (int i = 0; i < Geo::E; ++i) dst[F::out_index(tl, i)] = v[i];
+    for (int i = 0; i < Geo::E; ++i) bstore<C>(rout, v[i], vb, F::out_off(i) * sizeof(C));
   }
 }
 
@@ -131,7 +130,7 @@ __global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_cols(
   C v[Geo::E];
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) v[i] = in[base + n1_count * F::in_index(tl, i)];
-  F::run(v, lds + c * lds_size(L), tl, tw);
+  F::run(v, lds + c * lds_size(L), tl, F::twiddles(tw));
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) {
     const int64_t k2 = F::out_index(tl, i);
@@ -163,131 +162,195 @@ __global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_rows_t(
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) v[i] = reg[lds_pad(F::in_index(tl, i))];
   __syncthreads();
-  F::run(v, reg, tl, tw);
+  F::run(v, reg, tl, F::twiddles(tw));
   C* dst = out + int64_t(blockIdx.y) * seg_stride + k2_0 + c;
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) dst[n2_count * F::out_index(tl, i)] = v[i];
 }
 
-// Rebuild X[c] (c in [0, N/2]) of a real signal from the N/2-point FFT Z of
-// its even/odd pairs: X[c] = (Z[c] + Z*[N/2-c])/2 - (i/2) e^{-2 pi i c/N} (Z[c] - Z*[N/2-c]).
-template <typename C>
-__device__ __forceinline__ C real_spectrum_bin(const C* __restrict__ Z, int64_t half, int64_t c,
-                                               const Twiddle2<C>& tw2) {
-  const C zc = Z[c == half ? 0 : c];
-  const C zm = c_conj(Z[c == 0 ? 0 : half - c]);
-  const C a = c_add(zc, zm);
-  const C b = c_mul(tw2(c), c_sub(zc, zm));
-  const C x = c_add(a, c_mul_si<-1>(b));
-  return C{x.x * decltype(x.x)(0.5), x.y * decltype(x.x)(0.5)};
+// Real-signal spectrum from the N/2-point FFT Z of the even/odd pairs of a
+// segment, in place: for c in [0, N/2]
+//   X[c] = (Z[c] + Z*[N/2-c])/2 - (i/2) e^{-2 pi i c/N} (Z[c] - Z*[N/2-c])
+// (indices of Z mod N/2). Thread p owns the pair (p, N/2-p); the two real
+// values X[0] and X[N/2] share slot 0 as (X[0], X[N/2]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_twist(typename Complex<T>::type* __restrict__ Z, int64_t half,
+                                              Twiddle2<typename Complex<T>::type> tw2) {
+  using C = typename Complex<T>::type;
+  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p > half / 2) return;
+  C* z = Z + int64_t(blockIdx.y) * half;
+  const T h = T(0.5);
+  if (p == 0) {
+    const C z0 = z[0];
+    z[0] = C{z0.x + z0.y, z0.x - z0.y};
+    return;
+  }
+  const int64_t q = half - p;
+  const C zp = z[p], zq = z[q];
+  const C w = tw2(p);                           // e^{-2 pi i p/N}; at q it is -conj(w)
+  const C a = c_add(zp, c_conj(zq)), b = c_sub(zp, c_conj(zq));
+  const C xp = c_add(a, c_mul_si<-1>(c_mul(w, b)));
+  const C a2 = c_add(zq, c_conj(zp)), b2 = c_sub(zq, c_conj(zp));
+  const C xq = c_sub(a2, c_mul_si<-1>(c_mul(c_conj(w), b2)));
+  z[p] = C{xp.x * h, xp.y * h};
+  if (q != p) z[q] = C{xq.x * h, xq.y * h};
 }
 
-// Fused forward rows: gather + window + roll to baseband + N_out-point
-// inverse FFT + store. One transform per (segment, row).
-template <typename T, int L>
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
+// XCD i mod 8) and roughly in index order. Renumbering them so that XCD x
+// takes the x-th eighth of the units makes the workgroups resident on one XCD
+// at a time work on neighbouring rows, whose spectrum that XCD's L2 holds.
+__device__ __forceinline__ int xcd_major_block(int nblocks) {
+  const int b = blockIdx.x;
+  if (nblocks & 7) return b;
+  return (b & 7) * (nblocks >> 3) + (b >> 3);
+}
+
+// Fused forward rows: the windowed spectrum bins of a row are dropped at
+// their baseband slots (c - s_k) mod N_out (roll to baseband, crop, zero pad),
+// the N_out-point inverse FFT runs in registers and LDS, and the envelope row
+// is stored. One unit of G consecutive rows per workgroup.
+// ANALYTIC: the weight is scale_k (1 - (j/h_k)^2)^2 (bisquare, forward);
+// otherwise it comes from the packed table.
+template <typename T, int L, bool ANALYTIC>
 __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ Y,
-    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int64_t total_rows, int64_t half,
-    const typename Complex<T>::type* __restrict__ tw, Twiddle2<typename Complex<T>::type> tw2) {
+    const RowMeta* __restrict__ rows, const typename Complex<T>::type* __restrict__ roww,
+    const T* __restrict__ tab, int R, int total, int half, int sum_len, int64_t spec_elems,
+    const typename Complex<T>::type* __restrict__ tw, int nblocks) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, +1>;
   __shared__ C lds[Geo::G * lds_size(L)];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
-  const int64_t gr = int64_t(blockIdx.x) * Geo::G + g;
-  const bool ok = gr < total_rows;
-  const int64_t seg = ok ? gr / R : 0;
-  const RowMeta rm = rows[ok ? int(gr % R) : 0];
-  const C* Z = spec + seg * half;
+  const int u = xcd_major_block(nblocks);
+  const int gr = u * Geo::G + g;
+  const bool ok = gr < total;
+  const int seg = ok ? gr / R : 0;
+  const int row = ok ? gr - seg * R : 0;
+  const RowMeta rm = rows[row];
+  const rsrc_t rz = make_rsrc(spec, static_cast<uint32_t>(spec_elems * sizeof(C)));
+  const unsigned mask = static_cast<unsigned>(half - 1);
+  const unsigned zb = static_cast<unsigned>(seg) * static_cast<unsigned>(half);
+  const int cb = rm.s + tl;
+  // X[c] of the slots in the kept support; other slots get an offset beyond
+  // the buffer and read 0 without touching memory
   C v[Geo::E];
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) {
-    const int u = F::in_index(tl, i);
-    const int j = u < L / 2 ? u : u - L;
-    const int c = rm.s + j;
-    C val{0, 0};
-    if (ok && c >= rm.lo && c <= rm.hi) {
-      const T w = tab[rm.off + (c - rm.lo)];
-      const C x = real_spectrum_bin(Z, half, int64_t(c), tw2);
-      val = C{x.x * w, x.y * w};
-    }
-    v[i] = val;
+    const int off = F::in_off(i);
+    const int c = cb + (off < L / 2 ? off : off - L);   // slot tl + off holds offset j = slot or slot - L
+    const bool in = ok && c >= rm.lo && c <= rm.hi;
+    const unsigned vo = in ? (zb + (static_cast<unsigned>(c) & mask)) * static_cast<unsigned>(sizeof(C))
+                           : 0xFFFFFFFFu;
+    v[i] = bload<C>(rz, vo);
   }
-  F::run(v, lds + g * lds_size(L), tl, tw);
-  if (ok) {
-    C* dst = Y + gr * L;
+  const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
+  C sw{0, 0};
+  if constexpr (ANALYTIC) sw = roww[row];   // (scale_k, 1/h_k)
 #pragma unroll
-    for (int i = 0; i < Geo::E; ++i) dst[F::out_index(tl, i)] = v[i];
+  for (int i = 0; i < Geo::E; ++i) {
+    const int off = F::in_off(i);
+    const int j = tl + (off < L / 2 ? off : off - L);
+    const int c = rm.s + j;
+    C val = v[i];
+    if (c == 0) val.y = 0;               // slot 0 of the spectrum holds (X[0], X[N/2])
+    if (c == half) val = C{val.y, 0};
+    T w;
+    if constexpr (ANALYTIC) {
+      const T x = static_cast<T>(j) * sw.y;
+      const T b = (T(1) - x) * (T(1) + x);
+      w = sw.x * b * b;
+    } else {
+      const bool in = ok && c >= rm.lo && c <= rm.hi;
+      w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off - rm.lo + c : 0) * sizeof(T));
+    }
+    v[i] = C{val.x * w, val.y * w};
   }
+  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+  const int64_t r0 = int64_t(u) * Geo::G;
+  const int64_t nrow = total - r0 < Geo::G ? total - r0 : Geo::G;
+  const rsrc_t ry = make_rsrc(Y + r0 * L, static_cast<uint32_t>(nrow * L * sizeof(C)));
+  const uint32_t vb = static_cast<uint32_t>(g * L + tl) * sizeof(C);
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) bstore<C>(ry, v[i], vb, F::out_off(i) * sizeof(C));
 }
 
-// Inverse rows: N_out-point FFT of each envelope row, kept slots times the
+// Inverse rows: N_out-point FFT of each envelope row; the kept slots times the
 // table go to the packed per-segment buffer Sbuf[seg * sum_len + off + c - lo].
 template <typename T, int L>
 __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
     const typename Complex<T>::type* __restrict__ Y, typename Complex<T>::type* __restrict__ Sbuf,
-    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int64_t total_rows,
-    int64_t sum_len, const typename Complex<T>::type* __restrict__ tw) {
+    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int total, int sum_len, int segs,
+    const typename Complex<T>::type* __restrict__ tw) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, -1>;
   __shared__ C lds[Geo::G * lds_size(L)];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
-  const int64_t gr = int64_t(blockIdx.x) * Geo::G + g;
-  const bool ok = gr < total_rows;
+  const int64_t r0 = int64_t(blockIdx.x) * Geo::G;
+  const int64_t nrow = total - r0 < Geo::G ? total - r0 : Geo::G;
+  const rsrc_t ry = make_rsrc(Y + r0 * L, static_cast<uint32_t>(nrow * L * sizeof(C)));
+  const uint32_t vb = static_cast<uint32_t>(g * L + tl) * sizeof(C);
   C v[Geo::E];
-  if (ok) {
-    const C* src = Y + gr * L;
 #pragma unroll
-    for (int i = 0; i < Geo::E; ++i) v[i] = src[F::in_index(tl, i)];
-  } else {
-#pragma unroll
-    for (int i = 0; i < Geo::E; ++i) v[i] = C{0, 0};
-  }
-  F::run(v, lds + g * lds_size(L), tl, tw);
-  if (ok) {
-    const int64_t seg = gr / R;
-    const RowMeta rm = rows[int(gr % R)];
-    C* dst = Sbuf + seg * sum_len + rm.off - rm.lo;
-    const T* tb = tab + rm.off - rm.lo;
+  for (int i = 0; i < Geo::E; ++i) v[i] = bload<C>(ry, vb, F::in_off(i) * sizeof(C));
+  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+  const int gr = static_cast<int>(r0) + g;
+  if (gr < total) {
+    const int seg = gr / R;
+    const RowMeta rm = rows[gr - seg * R];
+    const int len = rm.hi - rm.lo + 1;
+    const rsrc_t rs = make_rsrc(Sbuf, static_cast<uint32_t>(int64_t(segs) * sum_len * sizeof(C)));
+    const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
+    const unsigned sb = static_cast<unsigned>(seg) * static_cast<unsigned>(sum_len) + static_cast<unsigned>(rm.off);
+    const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
-      const int u = F::out_index(tl, i);
-      const int j = u < L / 2 ? u : u - L;
-      const int c = rm.s + j;
-      if (c >= rm.lo && c <= rm.hi) {
-        const T w = tb[c];
-        dst[c] = C{v[i].x * w, v[i].y * w};
+      const int off = F::out_off(i);
+      const int d = db + (off < L / 2 ? off : off - L);
+      if (static_cast<unsigned>(d) < static_cast<unsigned>(len)) {
+        const T w = bload<T>(rt, (rm.off + d) * sizeof(T));
+        bstore<C>(rs, C{v[i].x * w, v[i].y * w}, (sb + d) * sizeof(C));
       }
     }
   }
 }
 
-// Overlap-add of the packed rows over the bins covered, in fixed row order,
-// followed by the pre-twist that turns the one-sided spectrum of bins p and
-// N/2-p into the half-size spectrum the synthesis FFT consumes.
+// Overlap-add of the packed rows over each bin, in ascending row order (no
+// atomics), through the per-bin list of packed-entry indices, followed by the
+// pre-twist that turns the one-sided spectrum at bins p and N/2-p into the
+// half-size spectrum the synthesis FFT consumes.
+template <typename C>
+__device__ __forceinline__ C bin_sum(const C* __restrict__ Sseg, const int* __restrict__ ent, int a, int b) {
+  C acc{0, 0};
+  int i = a;
+  for (; i + 4 <= b; i += 4) {
+    const int e0 = ent[i], e1 = ent[i + 1], e2 = ent[i + 2], e3 = ent[i + 3];
+    const C s0 = Sseg[e0], s1 = Sseg[e1], s2 = Sseg[e2], s3 = Sseg[e3];
+    acc = c_add(acc, s0);
+    acc = c_add(acc, s1);
+    acc = c_add(acc, s2);
+    acc = c_add(acc, s3);
+  }
+  for (; i < b; ++i) acc = c_add(acc, Sseg[ent[i]]);
+  return acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_ola(
     const typename Complex<T>::type* __restrict__ Sbuf, typename Complex<T>::type* __restrict__ Zout,
-    const RowMeta* __restrict__ rows, const int2* __restrict__ bins, int64_t half, int64_t sum_len,
+    const int* __restrict__ bin_start, const int* __restrict__ bin_ent, int64_t half, int64_t sum_len,
     Twiddle2<typename Complex<T>::type> tw2) {
   using C = typename Complex<T>::type;
   const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (p > half / 2) return;
   const int64_t seg = blockIdx.y;
   const C* Sseg = Sbuf + seg * sum_len;
-  auto bin_sum = [&](int64_t b) {
-    C acc{0, 0};
-    const int2 kr = bins[b];
-    for (int k = kr.x; k <= kr.y; ++k) {
-      const RowMeta rm = rows[k];
-      if (b >= rm.lo && b <= rm.hi) acc = c_add(acc, Sseg[rm.off + (b - rm.lo)]);
-    }
-    return acc;
-  };
   const int64_t q = half - p;
-  C A = bin_sum(p);
-  C B = bin_sum(q);
+  C A = bin_sum(Sseg, bin_ent, bin_start[p], bin_start[p + 1]);
+  C B = bin_sum(Sseg, bin_ent, bin_start[q], bin_start[q + 1]);
   if (p == 0) {   // DC and Nyquist: real parts only (irfft convention)
     A.y = 0;
     B.y = 0;
@@ -308,10 +371,10 @@ using namespace qtam;
 
 namespace {
 
-enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_FWD_ROWS, K_INV_ROWS, K_OLA, K_SYN, K_SYN1, K_SYN2, K_NUM };
+enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_TWIST, K_FWD_ROWS, K_INV_ROWS, K_OLA, K_SYN, K_SYN1, K_SYN2, K_NUM };
 const char* const kKindName[K_NUM] = {"spectrum_fft", "spectrum_fft_pass1", "spectrum_fft_pass2",
-                                       "fwd_rows", "inv_rows", "overlap_add", "synthesis_fft",
-                                       "synthesis_fft_pass1", "synthesis_fft_pass2"};
+                                       "spectrum_twist", "fwd_rows", "inv_rows", "overlap_add",
+                                       "synthesis_fft", "synthesis_fft_pass1", "synthesis_fft_pass2"};
 
 enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3 };
 
@@ -335,7 +398,9 @@ struct qtam_plan_s {
   char* dmem = nullptr;         // one allocation holding every device table
   // device table pointers (precision of the plan)
   RowMeta* d_rows = nullptr;
-  int2* d_bins = nullptr;
+  void* d_roww = nullptr;       // per row (scale, 1/h) of the analytic forward weight
+  int* d_bin_start = nullptr;   // [N/2+2] start of each bin's list of packed entries
+  int* d_bin_ent = nullptr;     // [sum_len] packed-entry index, ascending row per bin
   void* d_tab[4] = {};
   void* d_tw_out = nullptr;     // N_out
   void* d_tw_half = nullptr;    // N/2 (single pass) or nullptr
@@ -347,6 +412,8 @@ struct qtam_plan_s {
   bool four_step = false;
   int64_t n1 = 0, n2 = 0;
   bool gpu_supported = false;
+  bool analytic_fwd = false;    // bisquare: forward weights computed in the kernel
+  int num_cus = 0;
   qtam_status unsupported_reason = QTAM_OK;
   size_t seg_bytes = 0;         // workspace per segment (max over operations)
   // host info arrays
@@ -366,17 +433,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // Table construction for the device
 // ---------------------------------------------------------------------------
-template <typename T>
-void twiddles(std::vector<T>& out, int64_t L) {
-  // exp(-2 pi i m / L), interleaved, in FP64 then rounded once to T
-  out.resize(2 * L);
-  for (int64_t m = 0; m < L; ++m) {
-    const double a = -2.0 * M_PI * static_cast<double>(m) / static_cast<double>(L);
-    out[2 * m] = static_cast<T>(std::cos(a));
-    out[2 * m + 1] = static_cast<T>(std::sin(a));
-  }
-}
-
+// exp(-2 pi i m / L) for m = first, first + step, ... (count values),
+// interleaved, evaluated in FP64 and rounded once to T.
 template <typename T>
 void twiddles_strided(std::vector<T>& out, int64_t count, int64_t step, int64_t L) {
   out.resize(2 * count);
@@ -386,6 +444,29 @@ void twiddles_strided(std::vector<T>& out, int64_t count, int64_t step, int64_t 
     out[2 * m + 1] = static_cast<T>(std::sin(a));
   }
 }
+
+// Per-pass twiddle table of the block FFT of length L with e values per
+// thread, in the order the engine reads it (see BlockFft::tw_offset): for
+// each pass with stride ns > 1 and radix R, the base powers r = 1, 2, 4, 8
+// (< R) of exp(-2 pi i k / (ns R)), k in [0, ns).
+template <typename T>
+void stockham_twiddles(std::vector<T>& out, int64_t L, int64_t e) {
+  out.clear();
+  auto radix = [&](int64_t ns) { return (L / ns >= e) ? e : L / ns; };
+  for (int64_t ns = 1; ns < L; ns *= radix(ns)) {
+    const int64_t R = radix(ns);
+    if (ns == 1) continue;
+    for (int64_t r = 1; r < R; r *= 2)
+      for (int64_t k = 0; k < ns; ++k) {
+        const double a = -2.0 * M_PI * static_cast<double>(r * k) / static_cast<double>(ns * R);
+        out.push_back(static_cast<T>(std::cos(a)));
+        out.push_back(static_cast<T>(std::sin(a)));
+      }
+  }
+  if (out.empty()) out.assign(2, T(0));
+}
+
+int64_t engine_e(int64_t L, bool f64) { return std::min<int64_t>(L, f64 ? 8 : 16); }
 
 struct Blob {
   std::vector<char> bytes;
@@ -405,26 +486,46 @@ qtam_status upload(qtam_plan_s* pl) {
   for (int k = 0; k < hp.rows; ++k)
     rm[k] = RowMeta{hp.centre[k], hp.lo[k], hp.hi[k], static_cast<int>(hp.offset[k])};
   const size_t o_rows = blob.add(rm.data(), rm.size() * sizeof(RowMeta));
-  std::vector<int2> bins(hp.n_bins);
-  for (int64_t b = 0; b < hp.n_bins; ++b) bins[b] = int2{hp.bin_klo[b], hp.bin_khi[b]};
-  const size_t o_bins = blob.add(bins.data(), bins.size() * sizeof(int2));
+  // per-bin lists of the packed entries that cover the bin, rows ascending
+  std::vector<int> start(hp.n_bins + 2, 0), ent(hp.sum_len > 0 ? hp.sum_len : 1, 0);
+  for (int k = 0; k < hp.rows; ++k)
+    for (int64_t c = hp.lo[k]; c <= hp.hi[k]; ++c) ++start[c + 1];
+  for (int64_t b = 0; b < hp.n_bins; ++b) start[b + 1] += start[b];
+  start[hp.n_bins + 1] = start[hp.n_bins];
+  {
+    std::vector<int> fill(start.begin(), start.end() - 1);
+    for (int k = 0; k < hp.rows; ++k)
+      for (int64_t c = hp.lo[k]; c <= hp.hi[k]; ++c)
+        ent[fill[c]++] = static_cast<int>(hp.offset[k] + (c - hp.lo[k]));
+  }
+  const size_t o_bstart = blob.add(start.data(), start.size() * sizeof(int));
+  const size_t o_bent = blob.add(ent.data(), ent.size() * sizeof(int));
   size_t o_tab[4];
   const std::vector<double>* src[4] = {&hp.fwd_tab, &hp.dual_tab, &hp.afwd_tab, &hp.ainv_tab};
   for (int i = 0; i < 4; ++i) {
     std::vector<T> v(src[i]->begin(), src[i]->end());
     o_tab[i] = blob.add(v.data(), v.size() * sizeof(T));
   }
+  // per row (scale_k, 1/h_k): the forward weight at offset j is
+  // scale_k (1 - (j/h_k)^2)^2 for the bisquare window
+  std::vector<T> rw(2 * hp.rows);
+  for (int k = 0; k < hp.rows; ++k) {
+    rw[2 * k] = static_cast<T>(hp.fwd_tab[hp.offset[k] + (hp.centre[k] - hp.lo[k])]);
+    rw[2 * k + 1] = static_cast<T>(1.0 / static_cast<double>(hp.half_width[k]));
+  }
+  const size_t o_rw = blob.add(rw.data(), rw.size() * sizeof(T));
+  const bool f64 = sizeof(T) == 8;
   std::vector<T> tw;
-  twiddles(tw, hp.n_out);
+  stockham_twiddles(tw, hp.n_out, engine_e(hp.n_out, f64));
   const size_t o_out = blob.add(tw.data(), tw.size() * sizeof(T));
   size_t o_half = 0, o_n1 = 0, o_n2 = 0;
   if (!pl->four_step) {
-    twiddles(tw, hp.half);
+    stockham_twiddles(tw, hp.half, engine_e(hp.half, f64));
     o_half = blob.add(tw.data(), tw.size() * sizeof(T));
   } else {
-    twiddles(tw, pl->n1);
+    stockham_twiddles(tw, pl->n1, engine_e(pl->n1, f64));
     o_n1 = blob.add(tw.data(), tw.size() * sizeof(T));
-    twiddles(tw, pl->n2);
+    stockham_twiddles(tw, pl->n2, engine_e(pl->n2, f64));
     o_n2 = blob.add(tw.data(), tw.size() * sizeof(T));
   }
   // two-level table of exp(-2 pi i m / N)
@@ -447,7 +548,9 @@ qtam_status upload(qtam_plan_s* pl) {
   }
   char* d = pl->dmem;
   pl->d_rows = reinterpret_cast<RowMeta*>(d + o_rows);
-  pl->d_bins = reinterpret_cast<int2*>(d + o_bins);
+  pl->d_roww = d + o_rw;
+  pl->d_bin_start = reinterpret_cast<int*>(d + o_bstart);
+  pl->d_bin_ent = reinterpret_cast<int*>(d + o_bent);
   for (int i = 0; i < 4; ++i) pl->d_tab[i] = d + o_tab[i];
   pl->d_tw_out = d + o_out;
   pl->d_tw_half = pl->four_step ? nullptr : d + o_half;
@@ -494,8 +597,8 @@ struct Timed {
   X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
 
 template <typename T, int S>
-bool launch_fft_rows(int log2l, const void* in, void* out, int64_t count, int64_t in_stride,
-                     int64_t out_stride, const void* tw, hipStream_t st) {
+bool launch_fft_rows(int log2l, const void* in, void* out, int64_t count, int64_t stride, const void* tw,
+                     hipStream_t st) {
   using C = typename Complex<T>::type;
   switch (log2l) {
 #define X(LG)                                                                                      \
@@ -504,7 +607,7 @@ bool launch_fft_rows(int log2l, const void* in, void* out, int64_t count, int64_
       using Geo = RowGeom<T, (1 << LG)>;                                                           \
       const int64_t blocks = (count + Geo::G - 1) / Geo::G;                                        \
       hipLaunchKernelGGL((k_fft_rows<T, (1 << LG), S>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st, \
-                         static_cast<const C*>(in), static_cast<C*>(out), count, in_stride, out_stride, \
+                         static_cast<const C*>(in), static_cast<C*>(out), count, stride,            \
                          static_cast<const C*>(tw));                                               \
       return true;                                                                                 \
     }                                                                                              \
@@ -564,26 +667,28 @@ bool launch_fft_rows_t(int log2l, const void* in, void* out, int64_t n2, int64_t
 }
 
 template <typename T>
-bool launch_rows(bool forward, int log2l, const void* in, void* out, const RowMeta* rows, const void* tab,
-                 int R, int64_t total_rows, int64_t half, int64_t sum_len, const void* tw,
-                 Twiddle2<typename Complex<T>::type> tw2, hipStream_t st) {
+bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* out, const RowMeta* rows,
+                 const void* roww, const void* tab, int R, int64_t total_rows, int64_t half, int64_t sum_len,
+                 const void* tw, hipStream_t st) {
   using C = typename Complex<T>::type;
   switch (log2l) {
 #define X(LG)                                                                                          \
   case LG:                                                                                             \
     if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Single32 : kMaxLog2Single64)) {                    \
       using Geo = RowGeom<T, (1 << LG)>;                                                               \
-      const int64_t blocks = (total_rows + Geo::G - 1) / Geo::G;                                       \
-      if (forward)                                                                                     \
-        hipLaunchKernelGGL((k_fwd_rows<T, (1 << LG)>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st,   \
-                           static_cast<const C*>(in), static_cast<C*>(out), rows,                      \
-                           static_cast<const T*>(tab), R, total_rows, half, static_cast<const C*>(tw), \
-                           tw2);                                                                       \
-      else                                                                                             \
+      const int blocks = static_cast<int>((total_rows + Geo::G - 1) / Geo::G);                         \
+      if (forward) {                                                                                   \
+        auto kern = analytic ? k_fwd_rows<T, (1 << LG), true> : k_fwd_rows<T, (1 << LG), false>;      \
+        hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(Geo::NT), 0, st, static_cast<const C*>(in), \
+                           static_cast<C*>(out), rows, static_cast<const C*>(roww),                    \
+                           static_cast<const T*>(tab), R, int(total_rows), int(half), int(sum_len),    \
+                           (total_rows / R) * half, static_cast<const C*>(tw), blocks);                \
+      } else {                                                                                         \
         hipLaunchKernelGGL((k_inv_rows<T, (1 << LG)>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st,   \
                            static_cast<const C*>(in), static_cast<C*>(out), rows,                      \
-                           static_cast<const T*>(tab), R, total_rows, sum_len,                         \
-                           static_cast<const C*>(tw));                                                 \
+                           static_cast<const T*>(tab), R, int(total_rows), int(sum_len),               \
+                           int(total_rows / R), static_cast<const C*>(tw));                           \
+      }                                                                                                \
       return true;                                                                                     \
     }                                                                                                  \
     return false;
@@ -614,9 +719,21 @@ WsLayout layout_for(const qtam_plan_s* pl, int64_t segs) {
   return w;
 }
 
+// Largest number of segments whose signal, envelope and workspace regions each
+// stay below 2 GiB (kernels address them with 32-bit byte offsets).
+int64_t chunk_cap(const qtam_plan_s* pl) {
+  const HostPlan& hp = pl->hp;
+  const size_t rb = hp.precision == QTAM_FP64 ? 8 : 4;
+  const size_t per = std::max({size_t(hp.n) * rb, size_t(hp.rows) * size_t(hp.n_out) * 2 * rb,
+                               size_t(hp.sum_len) * 2 * rb});
+  const size_t lim = size_t(1) << 31;
+  return per > lim ? 0 : int64_t(lim / per);
+}
+
 int64_t chunk_for(const qtam_plan_s* pl, int64_t batch, size_t ws_bytes) {
   if (layout_for(pl, 1).total > ws_bytes) return 0;
-  int64_t lo = 1, hi = batch;
+  int64_t lo = 1, hi = std::min(batch, chunk_cap(pl));
+  if (hi < 1) return 0;
   while (lo < hi) {   // largest chunk whose layout fits
     const int64_t mid = lo + (hi - lo + 1) / 2;
     if (layout_for(pl, mid).total <= ws_bytes) lo = mid;
@@ -645,7 +762,7 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
   bool ok;
   if (!pl->four_step) {
     Timed tm(pl, K_SPEC, st);
-    ok = launch_fft_rows<T, -1>(ilog2(half), x, spec, segs, half, half, pl->d_tw_half, st);
+    ok = launch_fft_rows<T, -1>(ilog2(half), x, spec, segs, half, pl->d_tw_half, st);
   } else {
     void* tmp = ws + lay.tmp;
     {
@@ -658,9 +775,16 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
     }
   }
   if (!ok) return false;
+  {
+    using C = typename Complex<T>::type;
+    Timed tm(pl, K_TWIST, st);
+    hipLaunchKernelGGL((k_twist<T>), dim3(unsigned((half / 2 + 1 + 255) / 256), unsigned(segs)), dim3(256), 0, st,
+                       static_cast<C*>(spec), half, tw2_of<T>(pl));
+  }
   Timed tm(pl, K_FWD_ROWS, st);
-  return launch_rows<T>(true, ilog2(hp.n_out), spec, y, pl->d_rows, pl->d_tab[table], hp.rows,
-                        segs * hp.rows, half, hp.sum_len, pl->d_tw_out, tw2_of<T>(pl), st);
+  return launch_rows<T>(true, table == T_FWD && pl->analytic_fwd, ilog2(hp.n_out), spec, y, pl->d_rows,
+                        pl->d_roww, pl->d_tab[table], hp.rows, segs * hp.rows, half, hp.sum_len, pl->d_tw_out,
+                        st);
 }
 
 // synthesis: rows -> real signal (inverse with T_DUAL, forward adjoint with T_AFWD)
@@ -675,20 +799,20 @@ bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t s
   bool ok;
   {
     Timed tm(pl, K_INV_ROWS, st);
-    ok = launch_rows<T>(false, ilog2(hp.n_out), y, pack, pl->d_rows, pl->d_tab[table], hp.rows,
-                        segs * hp.rows, half, hp.sum_len, pl->d_tw_out, tw2_of<T>(pl), st);
+    ok = launch_rows<T>(false, false, ilog2(hp.n_out), y, pack, pl->d_rows, nullptr, pl->d_tab[table],
+                        hp.rows, segs * hp.rows, half, hp.sum_len, pl->d_tw_out, st);
   }
   if (!ok) return false;
   {
     Timed tm(pl, K_OLA, st);
     const int64_t pairs = half / 2 + 1;
     hipLaunchKernelGGL((k_ola<T>), dim3(unsigned((pairs + 255) / 256), unsigned(segs)), dim3(256), 0, st,
-                       static_cast<const C*>(pack), static_cast<C*>(spec), pl->d_rows, pl->d_bins, half,
-                       hp.sum_len, tw2_of<T>(pl));
+                       static_cast<const C*>(pack), static_cast<C*>(spec), pl->d_bin_start, pl->d_bin_ent,
+                       half, hp.sum_len, tw2_of<T>(pl));
   }
   if (!pl->four_step) {
     Timed tm(pl, K_SYN, st);
-    return launch_fft_rows<T, +1>(ilog2(half), spec, x, segs, half, half, pl->d_tw_half, st);
+    return launch_fft_rows<T, +1>(ilog2(half), spec, x, segs, half, pl->d_tw_half, st);
   }
   void* tmp = ws + lay.tmp;
   {
@@ -803,6 +927,12 @@ qtam_status qtam_plan_create(const qtam_params* params, qtam_plan_t* out) {
       delete pl;
       return QTAM_ERR_DEVICE;
     }
+    if (hipDeviceGetAttribute(&pl->num_cus, hipDeviceAttributeMultiprocessorCount, pl->device_id) != hipSuccess ||
+        pl->num_cus < 1) {
+      (void)hipGetLastError();
+      pl->num_cus = 1;
+    }
+    pl->analytic_fwd = pl->hp.window == QTAM_WIN_BISQUARE;
     st = pl->hp.precision == QTAM_FP64 ? upload<double>(pl) : upload<float>(pl);
     if (st != QTAM_OK) {
       if (pl->dmem) (void)hipFree(pl->dmem);

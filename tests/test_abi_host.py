@@ -1,0 +1,150 @@
+"""Host-side checks of the C ABI (no GPU needed): every symbol include/qtam.h
+declares is exported, host-only plans build the same tables as the oracle,
+and invalid calls return status codes without touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import paper_2603_29785_amd as qt
+from paper_2603_29785_amd import binding
+from oracle import oracle as o
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qtam.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qtam_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (qtam_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(binding.lib, n)
+    assert set(binding.EXPORTED) <= set(names)
+
+
+def test_status_strings_and_version():
+    for s in range(6):
+        assert qt.status_string(s)
+    assert qt.version().startswith("qtam-gfx950")
+
+
+def host_plan(**kw):
+    return qt.Plan(host_only=True, **kw)
+
+
+def compare_tables(gp, op):
+    t = op.row_table()
+    assert gp.N_out == op.N_out and gp.R == op.R
+    assert gp.info.sum_len == op.sum_len and gp.info.max_len == op.max_len
+    assert np.array_equal(gp.centre, t["centre"])
+    assert np.array_equal(gp.half_width, t["half"])
+    assert np.array_equal(gp.lo, t["lo"])
+    assert np.array_equal(gp.hi, t["hi"])
+    assert np.array_equal(gp.freqs, t["freq"])
+    W = op.windows()
+    assert np.abs(gp.windows_dense() - W).max() <= 1e-14 * np.abs(W).max()
+    P, M = op.frame()
+    assert np.abs(gp.frame - P).max() <= 1e-13 * P.max()
+    assert np.array_equal(gp.mask, M)
+    assert gp.info.l_max == op.l_max
+
+
+WORKLOAD_PLANS = [
+    dict(sample_rate=4096.0, n_samples=16384, q=8.0, f_min=20.0, f_max=1000.0, n_rows=64),
+    dict(sample_rate=4096.0, n_samples=131072, q=4.0, f_min=10.0, f_max=2048.0, n_rows=256),
+    dict(sample_rate=4096.0, n_samples=131072, q=16.0, f_min=10.0, f_max=2048.0, n_rows=256),
+    dict(sample_rate=8192.0, n_samples=2097152, q=12.0, f_min=5.0, f_max=4096.0, n_rows=512),
+    dict(sample_rate=4096.0, n_samples=32768, q=8.0, f_min=20.0, f_max=2000.0, n_rows=128),
+]
+
+
+@pytest.mark.parametrize("kw", WORKLOAD_PLANS)
+def test_workload_plan_tables_match_oracle(kw):
+    gp = host_plan(**kw)
+    op = o.OraclePlan(fs=kw["sample_rate"], n=kw["n_samples"], q=kw["q"], f_min=kw["f_min"],
+                      f_max=kw["f_max"], rows=kw["n_rows"])
+    compare_tables(gp, op)
+
+
+CAPS = {"cover": o.CAP_COVER, "paper": o.CAP_PAPER, "none": o.CAP_NONE}
+WINS = {"bisquare": o.WIN_BISQUARE, "hann": o.WIN_HANN, "kaiser": o.WIN_KAISER, "tukey": o.WIN_TUKEY,
+        "planck": o.WIN_PLANCK}
+
+
+@settings(max_examples=60, deadline=None)
+@given(log2n=st.integers(6, 14), rows=st.integers(1, 40), q=st.floats(0.5, 40.0),
+       fmin_frac=st.floats(0.02, 0.4), span=st.floats(1.0, 50.0), cap=st.sampled_from(list(CAPS)),
+       win=st.sampled_from(list(WINS)), param=st.floats(0.1, 0.9))
+def test_random_plan_tables_match_oracle(log2n, rows, q, fmin_frac, span, cap, win, param):
+    n = 2 ** log2n
+    fs = float(n) / 2.0          # T = 2 s
+    f_min = fmin_frac * fs / 2
+    f_max = min(f_min * span, fs / 2)
+    kw = dict(sample_rate=fs, n_samples=n, q=q, f_min=f_min, f_max=f_max, n_rows=rows, cap_mode=cap,
+              window=win, window_param=param * (8.0 if win == "kaiser" else 1.0))
+    try:
+        op = o.OraclePlan(fs=fs, n=n, q=q, f_min=f_min, f_max=f_max, rows=rows, cap_mode=CAPS[cap],
+                          window=WINS[win], window_param=kw["window_param"])
+    except ValueError:
+        with pytest.raises(qt.QtamError):
+            host_plan(**kw)
+        return
+    compare_tables(host_plan(**kw), op)
+
+
+def test_explicit_frequency_list_and_duplicates():
+    freqs = np.array([10.0, 10.0, 13.5, 20.0, 20.1, 44.0])
+    gp = host_plan(sample_rate=256.0, n_samples=1024, q=4.0, freqs=freqs)
+    op = o.OraclePlan(fs=256.0, n=1024, q=4.0, f_min=0, f_max=0, rows=6, freqs=freqs)
+    compare_tables(gp, op)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(sample_rate=0.0, n_samples=1024, q=4.0, f_min=10.0, f_max=100.0, n_rows=8),
+    dict(sample_rate=1024.0, n_samples=1023, q=4.0, f_min=10.0, f_max=100.0, n_rows=8),
+    dict(sample_rate=1024.0, n_samples=1024, q=-1.0, f_min=10.0, f_max=100.0, n_rows=8),
+    dict(sample_rate=1024.0, n_samples=1024, q=4.0, f_min=10.0, f_max=600.0, n_rows=8),
+    dict(sample_rate=1024.0, n_samples=1024, q=4.0, f_min=10.0, f_max=100.0, n_rows=0),
+    dict(sample_rate=1024.0, n_samples=1024, q=4.0, f_min=10.0, f_max=100.0, n_rows=8, n_out=8),
+    dict(sample_rate=1024.0, n_samples=1024, q=4.0, f_min=10.0, f_max=100.0, n_rows=8, cap_mode="manual"),
+])
+def test_invalid_parameters_rejected(kw):
+    with pytest.raises(qt.QtamError) as e:
+        host_plan(**kw)
+    assert e.value.status == binding.QTAM_ERR_INVALID_ARG
+
+
+def test_calls_without_device_return_status():
+    gp = host_plan(sample_rate=1024.0, n_samples=4096, q=8.0, f_min=10.0, f_max=400.0, n_rows=16)
+    L = binding.lib
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: the call fails validation first
+    ws = gp.workspace_bytes(2)
+    assert ws >= 2 * gp.info.workspace_bytes_per_segment - 2048
+    for fn in (L.qtam_forward, L.qtam_inverse, L.qtam_forward_adjoint, L.qtam_inverse_adjoint):
+        assert fn(gp._h, dummy, dummy, 2, dummy, ws, None) == binding.QTAM_ERR_INVALID_ARG
+        assert fn(gp._h, dummy, dummy, 0, dummy, ws, None) == binding.QTAM_OK     # empty batch
+        assert fn(gp._h, None, dummy, 2, dummy, ws, None) == binding.QTAM_ERR_INVALID_ARG
+        assert fn(None, dummy, dummy, 2, dummy, ws, None) == binding.QTAM_ERR_INVALID_ARG
+    assert L.qtam_plan_info(None, None) == binding.QTAM_ERR_INVALID_ARG
+    L.qtam_plan_destroy(None)
+
+
+def test_non_power_of_two_reports_unsupported_not_invalid():
+    gp = host_plan(sample_rate=4096.0, n_samples=24576, q=8.0, f_min=20.0, f_max=1000.0, n_rows=62)
+    dummy = ctypes.c_void_p(0x1000)
+    st_ = binding.lib.qtam_forward(gp._h, dummy, dummy, 1, dummy, 1 << 30, None)
+    assert st_ == binding.QTAM_ERR_UNSUPPORTED
