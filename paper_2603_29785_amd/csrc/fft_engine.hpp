@@ -160,9 +160,15 @@ __device__ __forceinline__ void dft_small(C* a) {
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
 constexpr int lds_size(int l) { return l + l / 32 + 1; }
 
+// Twiddle table layouts: TW_POW stores the base powers w^1, w^2, w^4, w^8 of
+// each pass and forms the others by products (little table traffic, for
+// kernels that stream their data); TW_FULL stores every w^r, r in [1, R)
+// (no products, for kernels whose vector ALU is the limit).
+enum TwiddleMode { TW_POW = 0, TW_FULL = 1 };
+
 // PREFETCH: request the twiddles of the next pass before the LDS exchange
 // (more registers live across the barrier) instead of after it.
-template <typename T, int L, int E, int S, bool PREFETCH = false>
+template <typename T, int L, int E, int S, int TW = TW_POW, bool PREFETCH = false>
 struct BlockFft {
   using C = typename Complex<T>::type;
   static_assert((L & (L - 1)) == 0 && (E & (E - 1)) == 0 && E <= L && E <= 16, "pow2 sizes");
@@ -175,8 +181,10 @@ struct BlockFft {
   }
   static constexpr int R0 = radix(1);
   static constexpr int RL = radix(last_ns());
-  // number of stored base powers w^(2^s) < R of a radix-R pass
-  static constexpr int slots(int r) { return r >= 16 ? 4 : r >= 8 ? 3 : r >= 4 ? 2 : r >= 2 ? 1 : 0; }
+  // number of stored powers of a radix-R pass: w^(2^s) < R, or all w^r, r < R
+  static constexpr int slots(int r) {
+    return TW == TW_FULL ? r - 1 : (r >= 16 ? 4 : r >= 8 ? 3 : r >= 4 ? 2 : r >= 2 ? 1 : 0);
+  }
   // start of the twiddle block of the pass with stride ns
   static constexpr int tw_offset(int ns) {
     int off = 0, n = 1;
@@ -203,22 +211,28 @@ struct BlockFft {
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
       const uint32_t k = static_cast<uint32_t>((tl + q * TPR) & (NS - 1));
-      C a[16];
+      if constexpr (TW == TW_FULL) {
 #pragma unroll
-      for (int sl = 0; sl < slots(R); ++sl)
-        a[1 << sl] = bload<C>(tw, k * sizeof(C), (tw_offset(NS) + sl * NS) * sizeof(C));
-      if constexpr (R > 2) a[3] = c_mul(a[2], a[1]);
-      if constexpr (R > 4) {
-        a[5] = c_mul(a[4], a[1]);
-        a[6] = c_mul(a[4], a[2]);
-        a[7] = c_mul(a[4], a[3]);
+        for (int r = 1; r < R; ++r)
+          w[q * R + r] = bload<C>(tw, k * sizeof(C), (tw_offset(NS) + (r - 1) * NS) * sizeof(C));
+      } else {
+        C a[16];
+#pragma unroll
+        for (int sl = 0; sl < slots(R); ++sl)
+          a[1 << sl] = bload<C>(tw, k * sizeof(C), (tw_offset(NS) + sl * NS) * sizeof(C));
+        if constexpr (R > 2) a[3] = c_mul(a[2], a[1]);
+        if constexpr (R > 4) {
+          a[5] = c_mul(a[4], a[1]);
+          a[6] = c_mul(a[4], a[2]);
+          a[7] = c_mul(a[4], a[3]);
+        }
+        if constexpr (R > 8) {
+#pragma unroll
+          for (int r = 9; r < 16; ++r) a[r] = c_mul(a[8], a[r - 8]);
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[q * R + r] = a[r];
       }
-      if constexpr (R > 8) {
-#pragma unroll
-        for (int r = 9; r < 16; ++r) a[r] = c_mul(a[8], a[r - 8]);
-      }
-#pragma unroll
-      for (int r = 1; r < R; ++r) w[q * R + r] = a[r];
     }
   }
 

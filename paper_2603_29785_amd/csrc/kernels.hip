@@ -211,8 +211,11 @@ __device__ __forceinline__ int xcd_major_block(int nblocks) {
 // their baseband slots (c - s_k) mod N_out (roll to baseband, crop, zero pad),
 // the N_out-point inverse FFT runs in registers and LDS, and the envelope row
 // is stored. One unit of G consecutive rows per workgroup.
-// ANALYTIC: the weight is scale_k (1 - (j/h_k)^2)^2 (bisquare, forward);
-// otherwise it comes from the packed table.
+// When a wave holds one row (TPR >= 64) and the row touches neither DC nor
+// Nyquist, buffer resources scoped to the row's kept support do the cropping:
+// slots outside it fall outside the resources and read 0, with no test.
+// Otherwise each slot is tested; ANALYTIC then computes the bisquare weight
+// scale_k (1 - (j/h_k)^2)^2 instead of reading the table.
 template <typename T, int L, bool ANALYTIC>
 __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ Y,
@@ -221,52 +224,69 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const typename Complex<T>::type* __restrict__ tw, int nblocks) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, +1>;
+  using F = BlockFft<T, L, Geo::E, +1, TW_POW>;
+  constexpr bool kWaveRow = Geo::TPR >= 64;   // every lane of a wave is on the same row
   __shared__ C lds[Geo::G * lds_size(L)];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
   const int u = xcd_major_block(nblocks);
-  const int gr = u * Geo::G + g;
+  int gr = u * Geo::G + g;
+  if constexpr (kWaveRow) gr = __builtin_amdgcn_readfirstlane(gr);
   const bool ok = gr < total;
   const int seg = ok ? gr / R : 0;
   const int row = ok ? gr - seg * R : 0;
   const RowMeta rm = rows[row];
-  const rsrc_t rz = make_rsrc(spec, static_cast<uint32_t>(spec_elems * sizeof(C)));
-  const unsigned mask = static_cast<unsigned>(half - 1);
-  const unsigned zb = static_cast<unsigned>(seg) * static_cast<unsigned>(half);
-  const int cb = rm.s + tl;
-  // X[c] of the slots in the kept support; other slots get an offset beyond
-  // the buffer and read 0 without touching memory
   C v[Geo::E];
+  if (kWaveRow && rm.lo > 0 && rm.hi < half) {
+    const int len = rm.hi - rm.lo + 1;
+    const rsrc_t rz = make_rsrc(spec + int64_t(seg) * half + rm.lo, ok ? static_cast<uint32_t>(len * sizeof(C)) : 0u);
+    const rsrc_t rt = make_rsrc(tab + rm.off, ok ? static_cast<uint32_t>(len * sizeof(T)) : 0u);
+    const int db = rm.s - rm.lo + tl;   // kept-bin index d = c - lo of the slot with offset 0
 #pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int off = F::in_off(i);
-    const int c = cb + (off < L / 2 ? off : off - L);   // slot tl + off holds offset j = slot or slot - L
-    const bool in = ok && c >= rm.lo && c <= rm.hi;
-    const unsigned vo = in ? (zb + (static_cast<unsigned>(c) & mask)) * static_cast<unsigned>(sizeof(C))
-                           : 0xFFFFFFFFu;
-    v[i] = bload<C>(rz, vo);
-  }
-  const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
-  C sw{0, 0};
-  if constexpr (ANALYTIC) sw = roww[row];   // (scale_k, 1/h_k)
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int off = F::in_off(i);
-    const int j = tl + (off < L / 2 ? off : off - L);
-    const int c = rm.s + j;
-    C val = v[i];
-    if (c == 0) val.y = 0;               // slot 0 of the spectrum holds (X[0], X[N/2])
-    if (c == half) val = C{val.y, 0};
-    T w;
-    if constexpr (ANALYTIC) {
-      const T x = static_cast<T>(j) * sw.y;
-      const T b = (T(1) - x) * (T(1) + x);
-      w = sw.x * b * b;
-    } else {
-      const bool in = ok && c >= rm.lo && c <= rm.hi;
-      w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off - rm.lo + c : 0) * sizeof(T));
+    for (int i = 0; i < Geo::E; ++i) {
+      const int off = F::in_off(i);
+      const unsigned d = static_cast<unsigned>(db + (off < L / 2 ? off : off - L));
+      const C x = bload<C>(rz, d * static_cast<unsigned>(sizeof(C)));
+      const T w = bload<T>(rt, d * static_cast<unsigned>(sizeof(T)));
+      v[i] = C{x.x * w, x.y * w};
     }
-    v[i] = C{val.x * w, val.y * w};
+  } else {
+    const rsrc_t rz = make_rsrc(spec, static_cast<uint32_t>(spec_elems * sizeof(C)));
+    const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
+    const unsigned mask = static_cast<unsigned>(half - 1);
+    const unsigned zb = static_cast<unsigned>(seg) * static_cast<unsigned>(half);
+    const int cb = rm.s + tl;
+    // X[c] of the slots in the kept support; other slots get an offset beyond
+    // the buffer and read 0 without touching memory
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) {
+      const int off = F::in_off(i);
+      const int c = cb + (off < L / 2 ? off : off - L);   // slot tl + off holds offset j = slot or slot - L
+      const bool in = ok && c >= rm.lo && c <= rm.hi;
+      const unsigned vo = in ? (zb + (static_cast<unsigned>(c) & mask)) * static_cast<unsigned>(sizeof(C))
+                             : 0xFFFFFFFFu;
+      v[i] = bload<C>(rz, vo);
+    }
+    C sw{0, 0};
+    if constexpr (ANALYTIC) sw = roww[row];   // (scale_k, 1/h_k)
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) {
+      const int off = F::in_off(i);
+      const int j = tl + (off < L / 2 ? off : off - L);
+      const int c = rm.s + j;
+      C val = v[i];
+      if (c == 0) val.y = 0;               // slot 0 of the spectrum holds (X[0], X[N/2])
+      if (c == half) val = C{val.y, 0};
+      T w;
+      if constexpr (ANALYTIC) {
+        const T x = static_cast<T>(j) * sw.y;
+        const T b = (T(1) - x) * (T(1) + x);
+        w = sw.x * b * b;
+      } else {
+        const bool in = ok && c >= rm.lo && c <= rm.hi;
+        w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off - rm.lo + c : 0) * sizeof(T));
+      }
+      v[i] = C{val.x * w, val.y * w};
+    }
   }
   F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
   const int64_t r0 = int64_t(u) * Geo::G;
@@ -279,6 +299,8 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
 
 // Inverse rows: N_out-point FFT of each envelope row; the kept slots times the
 // table go to the packed per-segment buffer Sbuf[seg * sum_len + off + c - lo].
+// With one row per wave, resources scoped to the row's packed entries drop
+// the other slots' stores without a test.
 template <typename T, int L>
 __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
     const typename Complex<T>::type* __restrict__ Y, typename Complex<T>::type* __restrict__ Sbuf,
@@ -286,7 +308,8 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
     const typename Complex<T>::type* __restrict__ tw) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, -1>;
+  using F = BlockFft<T, L, Geo::E, -1, TW_POW>;
+  constexpr bool kWaveRow = Geo::TPR >= 64;
   __shared__ C lds[Geo::G * lds_size(L)];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
   const int64_t r0 = int64_t(blockIdx.x) * Geo::G;
@@ -297,15 +320,27 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) v[i] = bload<C>(ry, vb, F::in_off(i) * sizeof(C));
   F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
-  const int gr = static_cast<int>(r0) + g;
-  if (gr < total) {
-    const int seg = gr / R;
-    const RowMeta rm = rows[gr - seg * R];
-    const int len = rm.hi - rm.lo + 1;
+  int gr = static_cast<int>(r0) + g;
+  if constexpr (kWaveRow) gr = __builtin_amdgcn_readfirstlane(gr);
+  if (gr >= total) return;
+  const int seg = gr / R;
+  const RowMeta rm = rows[gr - seg * R];
+  const int len = rm.hi - rm.lo + 1;
+  const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
+  if constexpr (kWaveRow) {
+    const rsrc_t rs = make_rsrc(Sbuf + int64_t(seg) * sum_len + rm.off, static_cast<uint32_t>(len * sizeof(C)));
+    const rsrc_t rt = make_rsrc(tab + rm.off, static_cast<uint32_t>(len * sizeof(T)));
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) {
+      const int off = F::out_off(i);
+      const unsigned d = static_cast<unsigned>(db + (off < L / 2 ? off : off - L));
+      const T w = bload<T>(rt, d * static_cast<unsigned>(sizeof(T)));
+      bstore<C>(rs, C{v[i].x * w, v[i].y * w}, d * static_cast<unsigned>(sizeof(C)));
+    }
+  } else {
     const rsrc_t rs = make_rsrc(Sbuf, static_cast<uint32_t>(int64_t(segs) * sum_len * sizeof(C)));
     const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
     const unsigned sb = static_cast<unsigned>(seg) * static_cast<unsigned>(sum_len) + static_cast<unsigned>(rm.off);
-    const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
       const int off = F::out_off(i);
@@ -402,7 +437,8 @@ struct qtam_plan_s {
   int* d_bin_start = nullptr;   // [N/2+2] start of each bin's list of packed entries
   int* d_bin_ent = nullptr;     // [sum_len] packed-entry index, ascending row per bin
   void* d_tab[4] = {};
-  void* d_tw_out = nullptr;     // N_out
+  void* d_tw_out = nullptr;     // N_out, base powers
+  void* d_tw_out_full = nullptr;  // N_out, every power
   void* d_tw_half = nullptr;    // N/2 (single pass) or nullptr
   void* d_tw_n1 = nullptr;      // N1 (four-step, second pass length)
   void* d_tw_n2 = nullptr;      // N2 (four-step, first pass length)
@@ -447,16 +483,17 @@ void twiddles_strided(std::vector<T>& out, int64_t count, int64_t step, int64_t 
 
 // Per-pass twiddle table of the block FFT of length L with e values per
 // thread, in the order the engine reads it (see BlockFft::tw_offset): for
-// each pass with stride ns > 1 and radix R, the base powers r = 1, 2, 4, 8
-// (< R) of exp(-2 pi i k / (ns R)), k in [0, ns).
+// each pass with stride ns > 1 and radix R, exp(-2 pi i r k / (ns R)),
+// k in [0, ns), for r = 1, 2, 4, 8 (< R) (TW_POW) or every r in [1, R)
+// (TW_FULL).
 template <typename T>
-void stockham_twiddles(std::vector<T>& out, int64_t L, int64_t e) {
+void stockham_twiddles(std::vector<T>& out, int64_t L, int64_t e, bool full) {
   out.clear();
   auto radix = [&](int64_t ns) { return (L / ns >= e) ? e : L / ns; };
   for (int64_t ns = 1; ns < L; ns *= radix(ns)) {
     const int64_t R = radix(ns);
     if (ns == 1) continue;
-    for (int64_t r = 1; r < R; r *= 2)
+    for (int64_t r = 1; r < R; r = full ? r + 1 : 2 * r)
       for (int64_t k = 0; k < ns; ++k) {
         const double a = -2.0 * M_PI * static_cast<double>(r * k) / static_cast<double>(ns * R);
         out.push_back(static_cast<T>(std::cos(a)));
@@ -516,16 +553,18 @@ qtam_status upload(qtam_plan_s* pl) {
   const size_t o_rw = blob.add(rw.data(), rw.size() * sizeof(T));
   const bool f64 = sizeof(T) == 8;
   std::vector<T> tw;
-  stockham_twiddles(tw, hp.n_out, engine_e(hp.n_out, f64));
+  stockham_twiddles(tw, hp.n_out, engine_e(hp.n_out, f64), false);
   const size_t o_out = blob.add(tw.data(), tw.size() * sizeof(T));
+  stockham_twiddles(tw, hp.n_out, engine_e(hp.n_out, f64), true);
+  const size_t o_out_full = blob.add(tw.data(), tw.size() * sizeof(T));
   size_t o_half = 0, o_n1 = 0, o_n2 = 0;
   if (!pl->four_step) {
-    stockham_twiddles(tw, hp.half, engine_e(hp.half, f64));
+    stockham_twiddles(tw, hp.half, engine_e(hp.half, f64), false);
     o_half = blob.add(tw.data(), tw.size() * sizeof(T));
   } else {
-    stockham_twiddles(tw, pl->n1, engine_e(pl->n1, f64));
+    stockham_twiddles(tw, pl->n1, engine_e(pl->n1, f64), false);
     o_n1 = blob.add(tw.data(), tw.size() * sizeof(T));
-    stockham_twiddles(tw, pl->n2, engine_e(pl->n2, f64));
+    stockham_twiddles(tw, pl->n2, engine_e(pl->n2, f64), false);
     o_n2 = blob.add(tw.data(), tw.size() * sizeof(T));
   }
   // two-level table of exp(-2 pi i m / N)
@@ -553,6 +592,7 @@ qtam_status upload(qtam_plan_s* pl) {
   pl->d_bin_ent = reinterpret_cast<int*>(d + o_bent);
   for (int i = 0; i < 4; ++i) pl->d_tab[i] = d + o_tab[i];
   pl->d_tw_out = d + o_out;
+  pl->d_tw_out_full = d + o_out_full;
   pl->d_tw_half = pl->four_step ? nullptr : d + o_half;
   pl->d_tw_n1 = pl->four_step ? d + o_n1 : nullptr;
   pl->d_tw_n2 = pl->four_step ? d + o_n2 : nullptr;
@@ -783,8 +823,8 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
   }
   Timed tm(pl, K_FWD_ROWS, st);
   return launch_rows<T>(true, table == T_FWD && pl->analytic_fwd, ilog2(hp.n_out), spec, y, pl->d_rows,
-                        pl->d_roww, pl->d_tab[table], hp.rows, segs * hp.rows, half, hp.sum_len, pl->d_tw_out,
-                        st);
+                        pl->d_roww, pl->d_tab[table], hp.rows, segs * hp.rows, half, hp.sum_len,
+                        pl->d_tw_out, st);
 }
 
 // synthesis: rows -> real signal (inverse with T_DUAL, forward adjoint with T_AFWD)
