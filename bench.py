@@ -39,6 +39,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the continuous-batching serving workload instead")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: Poisson arrival rate (1/s)")
+    ap.add_argument("--duration", type=float, default=30.0, help="serving: seconds of arrivals")
+    ap.add_argument("--hbm-budget-gb", type=float, default=32.0, help="serving: device memory budget")
+    ap.add_argument("--sweep", default="1000,5000,20000", help="serving: extra arrival rates for the saturation sweep")
     return ap.parse_args()
 
 
@@ -66,6 +72,8 @@ def main():
         print("bench.py measures one GPU: the transform shards by segment with no exchange, "
               "and this build runs on a single MI355X; use --gpus 1", file=sys.stderr)
         return 2
+    if args.serving:
+        return serving_main(args)
 
     import torch
     import paper_2603_29785_amd as qt
@@ -237,6 +245,107 @@ def cpu_leg(args, plans, x_host, x_dev, B, W):
     return {"cpu_baseline": cpu,
             "recon_rel_err": {"coef_max": max(errs_y), "recon_max": max(errs_x), "segments": done,
                               "vs": "FP64 CPU oracle", "precision": prec}}
+
+
+def serving_main(args):
+    """Poisson arrivals of segments of 1, 4, 16 or 64 s at 4096 or 16384 Hz,
+    Q in {4, 8, 16, 32}, 64-512 rows over 10-2048 Hz, FP32, through the
+    continuous-batching server; then a burst at saturation against the plain
+    one-segment-per-launch form on the same requests."""
+    import torch
+    import synthetic
+    from paper_2603_29785_amd.serving import BucketKey, GpuExecutor, Request, Server, plain_run
+
+    torch.cuda.set_device(0)
+    pool = {}
+    t0 = time.time()
+    for sec in (1, 4, 16, 64):
+        for fs in (4096.0, 16384.0):
+            n = int(sec * fs)
+            pool[(fs, n)] = [synthetic.injected_segment(n, fs, synthetic.rng_for(3, 100 * sec + j))[0]
+                             .astype(np.float32) for j in range(2)]
+    print("signal pool ready in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+
+    def key_of(a):
+        return BucketKey(a.fs, a.n, a.q, a.rows, 10.0, 2048.0)
+
+    def make(a, rid=[0]):
+        rid[0] += 1
+        return Request(rid[0], key_of(a), pool[(a.fs, a.n)][a.seed % 2])
+
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    ex = GpuExecutor(streams=4)
+    srv = Server(ex, hbm_budget=budget, streams=4)
+    arrivals = synthetic.serving_stream(rate=args.rate, duration=args.duration, seed=3000)
+    # warm-up: one burst per bucket so plans, buffers and graphs exist
+    keys = sorted({key_of(a) for a in arrivals}, key=lambda k: (k.n, k.q, k.rows, k.fs))
+    t0 = time.time()
+    for k in keys:
+        srv.submit(Request(-1, k, pool[(k.fs, k.n)][0]))
+    srv.drain(timeout=600)
+    for res in list(srv.resources.values()):
+        n = 1
+        while n <= res["slots"]:
+            ex._graph(res, n)
+            n *= 2
+    warm_rejected = sum(r.status == "rejected" for r in srv.done)
+    srv.done.clear()
+    srv.launches = 0
+    print("warm-up: %d buckets in %.1f s (%d shapes not on the device path)"
+          % (len(keys), time.time() - t0, warm_rejected), file=sys.stderr, flush=True)
+
+    srv.run_stream(arrivals, make, timeout=120)
+    st = srv.stats()
+    st["offered_rate"] = args.rate
+    st["offered_samples_per_s"] = sum(a.n for a in arrivals) / args.duration
+    print("serving at %g/s: %s" % (args.rate, st), file=sys.stderr, flush=True)
+
+    sweep = []
+    for rate in [float(r) for r in args.sweep.split(",") if r]:
+        srv.done.clear()
+        srv.launches = 0
+        arr = synthetic.serving_stream(rate=rate, duration=min(args.duration, 10.0), seed=4000)
+        srv.run_stream(arr, make, timeout=60)
+        s2 = srv.stats()
+        s2["offered_rate"] = rate
+        sweep.append({k: s2.get(k) for k in ("offered_rate", "completed", "p50_ms", "p99_ms", "samples_per_s")})
+        print("sweep %g/s: %s" % (rate, sweep[-1]), file=sys.stderr, flush=True)
+        if s2.get("p99_ms", 0) > 1000.0:
+            break
+
+    # saturation burst vs the plain form on the same requests
+    burst = [make(a) for a in synthetic.serving_stream(rate=1e6, duration=4e-4 * 1000, seed=5000)[:400]]
+    burst = [r for r in burst if r.key in srv.resources or r.key in ex.plans]
+    srv.done.clear()
+    srv.launches = 0
+    t0 = time.perf_counter()
+    for r in burst:
+        r.arrival = time.perf_counter()
+        srv.submit(r)
+    srv.drain(timeout=300)
+    t_srv = time.perf_counter() - t0
+    samples = sum(r.key.n for r in burst)
+    alone = [Request(r.rid, r.key, r.data) for r in burst]
+    t_plain = plain_run(alone, plans=ex.plans)
+    same = sum(np.array_equal(a.result, b.result) for a, b in zip(burst, alone))
+    srv.shutdown()
+    out = {
+        "metric": "fwd+inv QTAM samples/s @1 GPU; p50/p99 latency; recon rel-err vs FP64",
+        "value": samples / t_srv, "unit": "samples/s", "n_gpus": 1, "steps": len(burst), "warmup": len(keys),
+        "ms_per_step": 1e3 * t_srv / max(len(burst), 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving: Poisson %g req/s for %g s, 1/4/16/64 s at 4096/16384 Hz, Q in 4/8/16/32, "
+                               "64-512 rows 10-2048 Hz, FP32, HBM budget %g GB, 4 streams"
+                               % (args.rate, args.duration, args.hbm_budget_gb)},
+        "latency_ms": {"p50": st.get("p50_ms"), "p99": st.get("p99_ms"), "max": st.get("max_ms"),
+                       "what": "arrival to forward+inverse complete on the device (HIP event), incl. H2D"},
+        "serving": st, "sweep": sweep,
+        "saturation": {"requests": len(burst), "serving_samples_per_s": samples / t_srv,
+                       "plain_samples_per_s": samples / t_plain, "speedup": t_plain / t_srv,
+                       "identical_results": same},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 if __name__ == "__main__":

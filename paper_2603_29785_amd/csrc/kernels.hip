@@ -119,7 +119,7 @@ template <typename T, int L, int S>
 __global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_cols(
     const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
     int64_t n1_count, int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw,
-    Twiddle2<typename Complex<T>::type> tw2) {
+    Twiddle2<typename Complex<T>::type> tw2, int tw_mul) {
   using C = typename Complex<T>::type;
   using Geo = ColGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, S>;
@@ -134,7 +134,8 @@ __global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_cols(
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) {
     const int64_t k2 = F::out_index(tl, i);
-    C w = tw2(2 * n1 * k2);            // exp(-2 pi i n1 k2 / (N/2)) from the N-point table
+    // exp(-2 pi i n1 k2 / M), M = N1 N2, from the table of exp(-2 pi i m / (tw_mul M))
+    C w = tw2(tw_mul * n1 * k2);
     if constexpr (S > 0) w.y = -w.y;
     out[base + n1_count * k2] = c_mul(v[i], w);
   }
@@ -353,6 +354,95 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
   }
 }
 
+// Rows longer than one workgroup's LDS transform (four-step over the
+// workspace, N_out = L1 * L2, slot u = n1 + L1 n2, output m = k2 + L2 k1).
+// Forward, first pass: for every row, column n1 gathers its L2 slots from the
+// spectrum (windowed, zero outside the kept support), runs the length-L2
+// inverse FFT, multiplies by exp(+2 pi i n1 k2 / N_out) and stores A[n1 + L1 k2]
+// of the row. The second pass is k_fft_rows_t over the rows (lengths L1).
+template <typename T, int L2>
+__global__ __launch_bounds__((ColGeom<T, L2>::NT)) void k_fwd_rows_cols(
+    const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ A,
+    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int half, int64_t n_out, int64_t l1,
+    const typename Complex<T>::type* __restrict__ tw, Twiddle2<typename Complex<T>::type> tw2) {
+  using C = typename Complex<T>::type;
+  using Geo = ColGeom<T, L2>;
+  using F = BlockFft<T, L2, Geo::E, +1>;
+  __shared__ C lds[Geo::CC * lds_size(L2)];
+  const int t = threadIdx.x, cc = t % Geo::CC, tl = t / Geo::CC;
+  const int64_t n1 = int64_t(blockIdx.x) * Geo::CC + cc;
+  const int64_t gr = blockIdx.y;               // row of the chunk
+  const int64_t seg = gr / R;
+  const RowMeta rm = rows[int(gr - seg * R)];
+  const C* Z = spec + seg * half;
+  const int64_t hn = n_out / 2;
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int64_t u = n1 + l1 * F::in_index(tl, i);
+    const int64_t c = rm.s + (u < hn ? u : u - n_out);
+    C val{0, 0};
+    if (c >= rm.lo && c <= rm.hi) {
+      val = Z[c == half ? 0 : c];
+      if (c == 0) val.y = 0;                  // slot 0 holds (X[0], X[N/2])
+      if (c == half) val = C{val.y, 0};
+      const T w = tab[rm.off + (c - rm.lo)];
+      val = C{val.x * w, val.y * w};
+    }
+    v[i] = val;
+  }
+  F::run(v, lds + cc * lds_size(L2), tl, F::twiddles(tw));
+  C* dst = A + gr * n_out + n1;
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int64_t k2 = F::out_index(tl, i);
+    C w = tw2(n1 * k2);
+    w.y = -w.y;                               // exp(+2 pi i n1 k2 / N_out)
+    dst[l1 * k2] = c_mul(v[i], w);
+  }
+}
+
+// Inverse, second pass over long rows: length-L1 FFTs along the rows k2 of
+// the intermediate (CC rows per workgroup, staged through LDS), then the kept
+// output slots m = k2 + L2 k1 times the table go to the packed buffer.
+template <typename T, int L1>
+__global__ __launch_bounds__((ColGeom<T, L1>::NT)) void k_inv_rows_rowst(
+    const typename Complex<T>::type* __restrict__ A, typename Complex<T>::type* __restrict__ Sbuf,
+    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int64_t sum_len, int64_t n_out,
+    int64_t l2, const typename Complex<T>::type* __restrict__ tw) {
+  using C = typename Complex<T>::type;
+  using Geo = ColGeom<T, L1>;
+  using F = BlockFft<T, L1, Geo::E, -1>;
+  __shared__ C lds[Geo::CC * lds_size(L1)];
+  const int t = threadIdx.x;
+  const int64_t gr = blockIdx.y;
+  const int64_t k2_0 = int64_t(blockIdx.x) * Geo::CC;
+  const C* src = A + gr * n_out + k2_0 * L1;
+  for (int i = t; i < Geo::CC * L1; i += Geo::NT) lds[(i / L1) * lds_size(L1) + lds_pad(i % L1)] = src[i];
+  __syncthreads();
+  const int cc = t % Geo::CC, tl = t / Geo::CC;
+  C* reg = lds + cc * lds_size(L1);
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) v[i] = reg[lds_pad(F::in_index(tl, i))];
+  __syncthreads();
+  F::run(v, reg, tl, F::twiddles(tw));
+  const int64_t seg = gr / R;
+  const RowMeta rm = rows[int(gr - seg * R)];
+  C* dst = Sbuf + seg * sum_len + rm.off - rm.lo;
+  const T* tb = tab + rm.off - rm.lo;
+  const int64_t hn = n_out / 2;
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int64_t m = k2_0 + cc + l2 * F::out_index(tl, i);
+    const int64_t c = rm.s + (m < hn ? m : m - n_out);
+    if (c >= rm.lo && c <= rm.hi) {
+      const T w = tb[c];
+      dst[c] = C{v[i].x * w, v[i].y * w};
+    }
+  }
+}
+
 // Overlap-add of the packed rows over each bin, in ascending row order (no
 // atomics), through the per-bin list of packed-entry indices, followed by the
 // pre-twist that turns the one-sided spectrum at bins p and N/2-p into the
@@ -406,10 +496,12 @@ using namespace qtam;
 
 namespace {
 
-enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_TWIST, K_FWD_ROWS, K_INV_ROWS, K_OLA, K_SYN, K_SYN1, K_SYN2, K_NUM };
+enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_TWIST, K_FWD_ROWS, K_FWD_ROWS2, K_INV_ROWS, K_INV_ROWS2, K_OLA,
+            K_SYN, K_SYN1, K_SYN2, K_NUM };
 const char* const kKindName[K_NUM] = {"spectrum_fft", "spectrum_fft_pass1", "spectrum_fft_pass2",
-                                       "spectrum_twist", "fwd_rows", "inv_rows", "overlap_add",
-                                       "synthesis_fft", "synthesis_fft_pass1", "synthesis_fft_pass2"};
+                                       "spectrum_twist", "fwd_rows", "fwd_rows_pass2", "inv_rows",
+                                       "inv_rows_pass2", "overlap_add", "synthesis_fft",
+                                       "synthesis_fft_pass1", "synthesis_fft_pass2"};
 
 enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3 };
 
@@ -447,6 +539,13 @@ struct qtam_plan_s {
   int tw2_bits = 0;
   bool four_step = false;
   int64_t n1 = 0, n2 = 0;
+  bool big_rows = false;        // N_out beyond one workgroup: four-step rows through the workspace
+  int64_t r1 = 0, r2 = 0;       // N_out = r1 * r2
+  void* d_tw_r1 = nullptr;
+  void* d_tw_r2 = nullptr;
+  void* d_twr_fine = nullptr;   // two-level exp(-2 pi i m / N_out)
+  void* d_twr_coarse = nullptr;
+  int twr_bits = 0;
   bool gpu_supported = false;
   bool analytic_fwd = false;    // bisquare: forward weights computed in the kernel
   int num_cus = 0;
@@ -567,6 +666,20 @@ qtam_status upload(qtam_plan_s* pl) {
     stockham_twiddles(tw, pl->n2, engine_e(pl->n2, f64), false);
     o_n2 = blob.add(tw.data(), tw.size() * sizeof(T));
   }
+  size_t o_r1 = 0, o_r2 = 0, o_rf = 0, o_rc = 0;
+  if (pl->big_rows) {
+    stockham_twiddles(tw, pl->r1, engine_e(pl->r1, f64), false);
+    o_r1 = blob.add(tw.data(), tw.size() * sizeof(T));
+    stockham_twiddles(tw, pl->r2, engine_e(pl->r2, f64), false);
+    o_r2 = blob.add(tw.data(), tw.size() * sizeof(T));
+    const int nbr = ilog2(hp.n_out);
+    pl->twr_bits = (nbr + 1) / 2;
+    const int64_t nf = int64_t(1) << pl->twr_bits, ncs = int64_t(hp.n_out) >> pl->twr_bits;
+    twiddles_strided(tw, nf, 1, hp.n_out);
+    o_rf = blob.add(tw.data(), tw.size() * sizeof(T));
+    twiddles_strided(tw, ncs, nf, hp.n_out);
+    o_rc = blob.add(tw.data(), tw.size() * sizeof(T));
+  }
   // two-level table of exp(-2 pi i m / N)
   const int nb = ilog2(hp.n);
   pl->tw2_bits = (nb + 1) / 2;
@@ -596,6 +709,12 @@ qtam_status upload(qtam_plan_s* pl) {
   pl->d_tw_half = pl->four_step ? nullptr : d + o_half;
   pl->d_tw_n1 = pl->four_step ? d + o_n1 : nullptr;
   pl->d_tw_n2 = pl->four_step ? d + o_n2 : nullptr;
+  if (pl->big_rows) {
+    pl->d_tw_r1 = d + o_r1;
+    pl->d_tw_r2 = d + o_r2;
+    pl->d_twr_fine = d + o_rf;
+    pl->d_twr_coarse = d + o_rc;
+  }
   pl->d_tw2_fine = d + o_f;
   pl->d_tw2_coarse = d + o_c;
   return QTAM_OK;
@@ -664,7 +783,7 @@ constexpr int kMaxLog2Col64 = 11;   // and 2048 points (FP64)
 
 template <typename T, int S>
 bool launch_fft_cols(int log2l, const void* in, void* out, int64_t n1, int64_t segs, int64_t seg_stride,
-                     const void* tw, Twiddle2<typename Complex<T>::type> tw2, hipStream_t st) {
+                     const void* tw, Twiddle2<typename Complex<T>::type> tw2, hipStream_t st, int tw_mul = 2) {
   using C = typename Complex<T>::type;
   switch (log2l) {
 #define X(LG)                                                                                     \
@@ -674,7 +793,7 @@ bool launch_fft_cols(int log2l, const void* in, void* out, int64_t n1, int64_t s
       if (n1 % Geo::CC) return false;                                                             \
       hipLaunchKernelGGL((k_fft_cols<T, (1 << LG), S>), dim3(unsigned(n1 / Geo::CC), unsigned(segs)), \
                          dim3(Geo::NT), 0, st, static_cast<const C*>(in), static_cast<C*>(out), n1, \
-                         seg_stride, static_cast<const C*>(tw), tw2);                             \
+                         seg_stride, static_cast<const C*>(tw), tw2, tw_mul);                     \
       return true;                                                                                \
     }                                                                                             \
     return false;
@@ -738,11 +857,57 @@ bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* o
   }
 }
 
+template <typename T>
+bool launch_fwd_rows_cols(int log2l2, const void* spec, void* A, const RowMeta* rows, const void* tab, int R,
+                          int64_t total_rows, int64_t half, int64_t n_out, int64_t l1, const void* tw,
+                          Twiddle2<typename Complex<T>::type> tw2, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  switch (log2l2) {
+#define X(LG)                                                                                          \
+  case LG:                                                                                             \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                          \
+      using Geo = ColGeom<T, (1 << LG)>;                                                               \
+      if (l1 % Geo::CC) return false;                                                                  \
+      hipLaunchKernelGGL((k_fwd_rows_cols<T, (1 << LG)>), dim3(unsigned(l1 / Geo::CC), unsigned(total_rows)), \
+                         dim3(Geo::NT), 0, st, static_cast<const C*>(spec), static_cast<C*>(A), rows,  \
+                         static_cast<const T*>(tab), R, int(half), n_out, l1, static_cast<const C*>(tw), tw2); \
+      return true;                                                                                     \
+    }                                                                                                  \
+    return false;
+    QTAM_COL_CASES(X)
+#undef X
+    default: return false;
+  }
+}
+
+template <typename T>
+bool launch_inv_rows_rowst(int log2l1, const void* A, void* S, const RowMeta* rows, const void* tab, int R,
+                           int64_t total_rows, int64_t sum_len, int64_t n_out, int64_t l2, const void* tw,
+                           hipStream_t st) {
+  using C = typename Complex<T>::type;
+  switch (log2l1) {
+#define X(LG)                                                                                          \
+  case LG:                                                                                             \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                          \
+      using Geo = ColGeom<T, (1 << LG)>;                                                               \
+      if (l2 % Geo::CC) return false;                                                                  \
+      hipLaunchKernelGGL((k_inv_rows_rowst<T, (1 << LG)>), dim3(unsigned(l2 / Geo::CC), unsigned(total_rows)), \
+                         dim3(Geo::NT), 0, st, static_cast<const C*>(A), static_cast<C*>(S), rows,     \
+                         static_cast<const T*>(tab), R, sum_len, n_out, l2, static_cast<const C*>(tw)); \
+      return true;                                                                                     \
+    }                                                                                                  \
+    return false;
+    QTAM_COL_CASES(X)
+#undef X
+    default: return false;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Workspace layout for a chunk of segments
 // ---------------------------------------------------------------------------
 struct WsLayout {
-  size_t spec = 0, tmp = 0, pack = 0, total = 0;
+  size_t spec = 0, tmp = 0, pack = 0, rows = 0, total = 0;
 };
 
 WsLayout layout_for(const qtam_plan_s* pl, int64_t segs) {
@@ -755,6 +920,8 @@ WsLayout layout_for(const qtam_plan_s* pl, int64_t segs) {
   if (pl->four_step) off = align256(off + size_t(segs) * size_t(pl->hp.half) * cb);
   w.pack = off;
   off = align256(off + size_t(segs) * size_t(pl->hp.sum_len) * cb);
+  w.rows = off;
+  if (pl->big_rows) off = align256(off + size_t(segs) * size_t(pl->hp.rows) * size_t(pl->hp.n_out) * cb);
   w.total = off;
   return w;
 }
@@ -767,7 +934,9 @@ int64_t chunk_cap(const qtam_plan_s* pl) {
   const size_t per = std::max({size_t(hp.n) * rb, size_t(hp.rows) * size_t(hp.n_out) * 2 * rb,
                                size_t(hp.sum_len) * 2 * rb});
   const size_t lim = size_t(1) << 31;
-  return per > lim ? 0 : int64_t(lim / per);
+  int64_t cap = per > lim ? 0 : int64_t(lim / per);
+  if (pl->big_rows) cap = std::min<int64_t>(cap, 65535 / hp.rows);   // rows of a chunk index grid.y
+  return cap;
 }
 
 int64_t chunk_for(const qtam_plan_s* pl, int64_t batch, size_t ws_bytes) {
@@ -821,6 +990,20 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
     hipLaunchKernelGGL((k_twist<T>), dim3(unsigned((half / 2 + 1 + 255) / 256), unsigned(segs)), dim3(256), 0, st,
                        static_cast<C*>(spec), half, tw2_of<T>(pl));
   }
+  if (pl->big_rows) {
+    using C = typename Complex<T>::type;
+    const Twiddle2<C> twr{static_cast<const C*>(pl->d_twr_fine), static_cast<const C*>(pl->d_twr_coarse),
+                          pl->twr_bits};
+    void* A = ws + lay.rows;
+    {
+      Timed tm(pl, K_FWD_ROWS, st);
+      if (!launch_fwd_rows_cols<T>(ilog2(pl->r2), spec, A, pl->d_rows, pl->d_tab[table], hp.rows,
+                                   segs * hp.rows, half, hp.n_out, pl->r1, pl->d_tw_r2, twr, st))
+        return false;
+    }
+    Timed tm(pl, K_FWD_ROWS2, st);
+    return launch_fft_rows_t<T, +1>(ilog2(pl->r1), A, y, pl->r2, segs * hp.rows, hp.n_out, pl->d_tw_r1, st);
+  }
   Timed tm(pl, K_FWD_ROWS, st);
   return launch_rows<T>(true, table == T_FWD && pl->analytic_fwd, ilog2(hp.n_out), spec, y, pl->d_rows,
                         pl->d_roww, pl->d_tab[table], hp.rows, segs * hp.rows, half, hp.sum_len,
@@ -837,7 +1020,20 @@ bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t s
   void* spec = ws + lay.spec;
   void* pack = ws + lay.pack;
   bool ok;
-  {
+  if (pl->big_rows) {
+    const Twiddle2<C> twr{static_cast<const C*>(pl->d_twr_fine), static_cast<const C*>(pl->d_twr_coarse),
+                          pl->twr_bits};
+    void* A = ws + lay.rows;
+    {
+      Timed tm(pl, K_INV_ROWS, st);
+      ok = launch_fft_cols<T, -1>(ilog2(pl->r2), y, A, pl->r1, segs * hp.rows, hp.n_out, pl->d_tw_r2, twr, st, 1);
+    }
+    if (ok) {
+      Timed tm(pl, K_INV_ROWS2, st);
+      ok = launch_inv_rows_rowst<T>(ilog2(pl->r1), A, pack, pl->d_rows, pl->d_tab[table], hp.rows,
+                                    segs * hp.rows, hp.sum_len, hp.n_out, pl->r2, pl->d_tw_r1, st);
+    }
+  } else {
     Timed tm(pl, K_INV_ROWS, st);
     ok = launch_rows<T>(false, false, ilog2(hp.n_out), y, pack, pl->d_rows, nullptr, pl->d_tab[table],
                         hp.rows, segs * hp.rows, half, hp.sum_len, pl->d_tw_out, st);
@@ -911,7 +1107,14 @@ void choose_geometry(qtam_plan_s* pl) {
   pl->unsupported_reason = QTAM_ERR_UNSUPPORTED;
   if (!is_pow2(hp.n) || !is_pow2(hp.n_out)) return;
   const int ln = ilog2(hp.n_out);
-  if (ln < 2 || ln > max_single) return;
+  if (ln < 2) return;
+  pl->big_rows = ln > max_single;
+  if (pl->big_rows) {
+    const int l2 = ln / 2, l1 = ln - l2;   // N_out = r1 * r2, r1 >= r2
+    pl->r1 = int64_t(1) << l1;
+    pl->r2 = int64_t(1) << l2;
+    if (l1 > (f64 ? kMaxLog2Col64 : kMaxLog2Col32) || hp.rows > 65535) return;
+  }
   const int lh = ilog2(hp.half);
   if (lh < 3) return;
   if (lh <= std::min(max_single, 13)) {

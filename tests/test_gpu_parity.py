@@ -204,3 +204,30 @@ def test_errors_and_empty(torch_dev):
     with pytest.raises(qt.QtamError) as e:
         bad.forward(torch.zeros(1, 24576, device="cuda"))
     assert e.value.status == 2
+
+
+LONG_ROWS = [
+    # rows longer than one workgroup's LDS transform: four-step rows
+    ("fp32", 16384.0, 1 << 20, 8.0, 10.0, 2048.0, 64, 2),      # 64 s at 16384 Hz, 64 rows: N_out 32768
+    ("fp64", 4096.0, 1 << 18, 4.0, 10.0, 2048.0, 64, 1),       # FP64 N_out 16384
+    ("fp32", 8192.0, 1 << 21, 12.0, 5.0, 4096.0, 512, 1),      # long-segment precision workload plan
+    ("fp64", 8192.0, 1 << 21, 12.0, 5.0, 4096.0, 512, 1),
+]
+
+
+@pytest.mark.parametrize("case", LONG_ROWS, ids=[f"{c[0]}_N{c[2]}_R{c[6]}" for c in LONG_ROWS])
+def test_long_rows_parity(torch_dev, case):
+    torch = torch_dev
+    precision, fs, n, q, fmin, fmax, R, B = case
+    gp, op = plans(fs, n, q, fmin, fmax, R, precision)
+    print(f"long rows: N={n} R={R} N_out={gp.N_out} {precision}", flush=True)
+    x = np.stack([synthetic.injected_segment(n, fs, synthetic.rng_for(12, i))[0] for i in range(B)])
+    xh = host_input(x, precision)
+    Y = gp.forward(to_dev(torch, xh, precision))
+    xr = gp.inverse(Y).cpu().numpy()
+    Y = Y.cpu().numpy()
+    for b in range(B):
+        Yr = op.forward(xh[b])
+        assert rel(Y[b], Yr) <= TOL[precision], b
+        xo = op.inverse(Yr)
+        assert rel(xr[b], xo) <= TOL[precision] * (10 if precision == "fp32" else 1), b
