@@ -52,7 +52,8 @@ def lib():
                                       ctypes.c_double, ctypes.c_double, ctypes.c_int32, dp,
                                       ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                      ctypes.c_double]
+                                      ctypes.c_double, ctypes.c_int32, dp,
+                                      ctypes.POINTER(ctypes.c_int32), dp]
         L.ora_plan_destroy.argtypes = [ctypes.c_void_p]
         L.ora_plan_sizes.argtypes = [ctypes.c_void_p, i64p]
         L.ora_plan_rows.argtypes = [ctypes.c_void_p, dp, i64p, i64p, i64p, i64p]
@@ -100,6 +101,7 @@ class OraclePlan:
     norm_mode: int = NORM_UNIT_ENERGY
     n_out: int = 0
     p_floor_rel: float = 1e-6
+    planes: list | None = None     # [(q, window, param), ...]: composite bank, plane after plane
 
     def __post_init__(self):
         L = lib()
@@ -108,10 +110,21 @@ class OraclePlan:
             self._freqs = np.ascontiguousarray(self.freqs, dtype=np.float64)
             fr = _dp(self._freqs)
             self.rows = int(self._freqs.size)
+        npl, qs, ws, ps = 0, None, None, None
+        if self.planes:
+            npl = len(self.planes)
+            self._qs = np.array([p[0] for p in self.planes], dtype=np.float64)
+            self._ws = np.array([p[1] for p in self.planes], dtype=np.int32)
+            self._ps = np.array([p[2] for p in self.planes], dtype=np.float64)
+            qs, ps = _dp(self._qs), _dp(self._ps)
+            ws = self._ws.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        self.n_planes = max(npl, 1)
+        self.rows_per_plane = int(self.rows)
         h = L.ora_plan_create(float(self.fs), int(self.n), float(self.q), float(self.f_min),
                               float(self.f_max), int(self.rows), fr, int(self.window),
                               float(self.window_param), int(self.cap_mode), int(self.max_window),
-                              int(self.norm_mode), int(self.n_out), float(self.p_floor_rel))
+                              int(self.norm_mode), int(self.n_out), float(self.p_floor_rel),
+                              int(npl), qs, ws, ps)
         if not h:
             raise ValueError("oracle rejected the plan parameters")
         self._h = ctypes.c_void_p(h)
@@ -191,3 +204,30 @@ class OraclePlan:
         _, M = self.frame()
         X = self.spectrum(x)
         return self.synthesis(X * M)
+
+    # ------------------------------------------------------- composite banks
+    # Multi-Q / multi-window extension (App. A): the bank's planes are
+    # consecutive blocks of rows_per_plane rows; each plane is scored by a
+    # quality metric, and the optimal-selection mode keeps, for every
+    # segment on its own, the plane with the best score.
+
+    def row_stats(self, Y):
+        """(energy, peak) per row: sum and max over m of |Y_k[m]|^2."""
+        a = np.abs(np.asarray(Y, dtype=np.complex128)) ** 2
+        return a.sum(axis=-1), a.max(axis=-1)
+
+    def plane_scores(self, Y, kind: str = "energy"):
+        """Score of each plane, shape [..., n_planes]."""
+        energy, peak = self.row_stats(Y)
+        per = (energy if kind == "energy" else peak)
+        per = per.reshape(per.shape[:-1] + (self.n_planes, self.rows_per_plane))
+        return per.sum(axis=-1) if kind == "energy" else per.max(axis=-1)
+
+    def select_planes(self, Y, kind: str = "energy"):
+        """(score, best, Y_best): the first plane with the largest score."""
+        Y = np.asarray(Y)
+        score = self.plane_scores(Y, kind)
+        best = np.argmax(score, axis=-1)
+        Yp = Y.reshape(Y.shape[:-2] + (self.n_planes, self.rows_per_plane, Y.shape[-1]))
+        Yb = np.take_along_axis(Yp, best[..., None, None, None], axis=-3)[..., 0, :, :]
+        return score, best, Yb

@@ -180,15 +180,25 @@ int64_t next_pow2(int64_t v) {
   return p;
 }
 
-// Returns 0 on success, 1 on invalid parameters.
-int build_plan(Plan& pl, double fs, int64_t n, double q, double fmin, double fmax,
-               int32_t nrows, const double* freqs, int32_t window, double window_param,
-               int32_t cap_mode, int32_t max_window, int32_t norm_mode, int32_t n_out,
-               double tau) {
-  if (!(fs > 0.0) || n < 4 || (n % 2) != 0 || !(q > 0.0) || nrows < 1) return 1;
+// One plane of a composite bank: its quality factor and window (App. A,
+// multi-Q / multi-window extension). A plain plan has one plane.
+struct PlaneSpec {
+  double q;
+  int32_t window;
+  double param;
+};
+
+// Returns 0 on success, 1 on invalid parameters. Rows are plane after plane,
+// each plane over the same frequency grid.
+int build_plan(Plan& pl, double fs, int64_t n, const std::vector<PlaneSpec>& planes, double fmin,
+               double fmax, int32_t nrows, const double* freqs, int32_t cap_mode, int32_t max_window,
+               int32_t norm_mode, int32_t n_out, double tau) {
+  if (!(fs > 0.0) || n < 4 || (n % 2) != 0 || nrows < 1 || planes.empty()) return 1;
+  for (const PlaneSpec& ps : planes)
+    if (!(ps.q > 0.0)) return 1;
+  pl.q = planes[0].q;
   pl.fs = fs;
   pl.n = n;
-  pl.q = q;
   pl.nbins = n / 2 + 1;
   pl.tau = tau;
   const double T = static_cast<double>(n) / fs;   // segment duration N_t
@@ -237,7 +247,11 @@ int build_plan(Plan& pl, double fs, int64_t n, double q, double fmin, double fma
   pl.rows.clear();
   const int64_t half_bins = n / 2;
   int64_t max_len = 0;
+  for (size_t plane = 0; plane < planes.size(); ++plane)
   for (int32_t k = 0; k < nrows; ++k) {
+    const double q = planes[plane].q;
+    const int32_t window = planes[plane].window;
+    const double window_param = planes[plane].param;
     Row r;
     r.f = f[static_cast<size_t>(k)];
     // O2 centre bin: k_c = f * N_t (Sec. II), rounded to the nearest integer
@@ -409,12 +423,20 @@ void dense_one(const Plan& pl, const double* x, cd* T) {
 // ---------------------------------------------------------------------------
 extern "C" {
 
+// n_planes > 0: plane p has quality factor qs[p], window windows[p] with
+// parameter params[p]; otherwise one plane (q, window, window_param).
 void* ora_plan_create(double fs, int64_t n, double q, double fmin, double fmax, int32_t nrows,
                       const double* freqs, int32_t window, double window_param, int32_t cap_mode,
-                      int32_t max_window, int32_t norm_mode, int32_t n_out, double tau) {
+                      int32_t max_window, int32_t norm_mode, int32_t n_out, double tau,
+                      int32_t n_planes, const double* qs, const int32_t* windows, const double* params) {
+  std::vector<PlaneSpec> planes;
+  if (n_planes > 0)
+    for (int32_t p = 0; p < n_planes; ++p) planes.push_back(PlaneSpec{qs[p], windows[p], params[p]});
+  else
+    planes.push_back(PlaneSpec{q, window, window_param});
   Plan* pl = new Plan();
-  if (build_plan(*pl, fs, n, q, fmin, fmax, nrows, freqs, window, window_param, cap_mode,
-                 max_window, norm_mode, n_out, tau) != 0) {
+  if (build_plan(*pl, fs, n, planes, fmin, fmax, nrows, freqs, cap_mode, max_window, norm_mode, n_out,
+                 tau) != 0) {
     delete pl;
     return nullptr;
   }

@@ -347,3 +347,90 @@ def test_pure_sinusoid_closed_form():
     assert int(np.argmax(np.abs(Y).max(axis=1))) == k0
     # the carrier offset is removed: row k0 is constant in time, phase 0
     assert np.allclose(Y[k0], amp[k0], rtol=1e-12, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Composite multi-Q / multi-window banks (App. A extension): planes are
+# independent analyses of one spectrum, the frame is their sum, and the
+# plane metrics follow from Parseval and from a pure tone.
+# --------------------------------------------------------------------------
+COMPOSITE = [(4.0, o.WIN_BISQUARE, 0.0), (8.0, o.WIN_HANN, 0.0), (16.0, o.WIN_TUKEY, 0.5)]
+
+
+def composite_plan(**kw):
+    base = dict(fs=1024.0, n=4096, q=1.0, f_min=20.0, f_max=400.0, rows=24, planes=COMPOSITE)
+    base.update(kw)
+    return o.OraclePlan(**base)
+
+
+def test_composite_planes_are_single_plans():
+    pc = composite_plan()
+    assert pc.R == 3 * 24 and pc.n_planes == 3 and pc.rows_per_plane == 24
+    x = np.random.default_rng(31).standard_normal(pc.n)
+    Yc = pc.forward(x)
+    P_sum = np.zeros(pc.n // 2 + 1)
+    for i, (q, w, a) in enumerate(COMPOSITE):
+        ps = o.OraclePlan(fs=1024.0, n=4096, q=q, f_min=20.0, f_max=400.0, rows=24, window=w, window_param=a,
+                          n_out=pc.N_out)
+        # forward rows do not see the other planes
+        assert np.array_equal(Yc[24 * i:24 * (i + 1)], ps.forward(x))
+        P_sum += ps.frame()[0]
+    # the bank's frame operator is the sum of the planes' ones
+    assert rel(pc.frame()[0], P_sum) < 1e-14
+
+
+def test_composite_exact_reconstruction():
+    pc = composite_plan()
+    x = np.random.default_rng(32).standard_normal(pc.n)
+    xm = pc.project(x)
+    assert rel(pc.inverse(pc.forward(x)), xm) < 1e-12
+    # the bank covers more bins than its narrowest plane
+    ps = o.OraclePlan(fs=1024.0, n=4096, q=16.0, f_min=20.0, f_max=400.0, rows=24, window=o.WIN_TUKEY,
+                      window_param=0.5)
+    assert pc.frame()[1].sum() >= ps.frame()[1].sum()
+
+
+def test_row_energy_is_parseval_of_windowed_spectrum():
+    pc = composite_plan()
+    x = np.random.default_rng(33).standard_normal(pc.n)
+    energy, _ = pc.row_stats(pc.forward(x))
+    X = np.fft.rfft(x)                       # numpy, not the oracle's spectrum
+    W = pc.windows()
+    expect = np.sum(np.abs(W * X[None, :]) ** 2, axis=1) / pc.n
+    assert rel(energy, expect) < 1e-12
+
+
+def test_plane_scores_of_a_pure_tone():
+    """A tone at bin b0 gives |Y_k[m]|^2 = (sqrt(N/N_out) W_k[b0] / 2)^2 for
+    every m, so the peak score of plane p is max_k of that and the energy
+    score is N/4 times the plane's frame operator at b0."""
+    pc = composite_plan()
+    N, M = pc.n, pc.N_out
+    b0 = 300
+    x = np.cos(2 * np.pi * b0 * np.arange(N) / N)
+    Y = pc.forward(x)
+    W = pc.windows()[:, b0].reshape(3, 24)
+    peak = pc.plane_scores(Y, "peak")
+    energy = pc.plane_scores(Y, "energy")
+    assert np.allclose(peak, (0.5 * math.sqrt(N / M) * W.max(axis=1)) ** 2, rtol=1e-12)
+    assert np.allclose(energy, N / 4.0 * np.sum(W ** 2, axis=1), rtol=1e-12)
+    _, best, Yb = pc.select_planes(Y, "energy")
+    assert best == int(np.argmax(np.sum(W ** 2, axis=1)))
+    assert np.array_equal(Yb, Y[24 * best:24 * (best + 1)])
+
+
+def test_selection_is_per_segment():
+    """A long steady tone favours the highest-Q plane under the peak metric;
+    a short click favours the lowest-Q plane; in one batch each segment
+    keeps its own plane."""
+    pc = composite_plan(planes=[(2.0, o.WIN_BISQUARE, 0.0), (32.0, o.WIN_BISQUARE, 0.0)])
+    N = pc.n
+    b0 = int(pc.row_table()["centre"][10])       # on a row centre, where the Q = 32 plane has no hole
+    tone = np.cos(2 * np.pi * (b0 + 0.25) * np.arange(N) / N)
+    click = np.zeros(N)
+    click[N // 2] = 50.0
+    Y = pc.forward(np.stack([tone, click]))
+    _, best, Yb = pc.select_planes(Y, "peak")
+    assert list(best) == [1, 0]
+    R = pc.rows_per_plane
+    assert np.array_equal(Yb[0], Y[0, R:2 * R]) and np.array_equal(Yb[1], Y[1, :R])
