@@ -45,7 +45,54 @@ def parse():
     ap.add_argument("--duration", type=float, default=30.0, help="serving: seconds of arrivals")
     ap.add_argument("--hbm-budget-gb", type=float, default=32.0, help="serving: device memory budget")
     ap.add_argument("--sweep", default="1000,5000,20000", help="serving: extra arrival rates for the saturation sweep")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain device copy of 1 GiB (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+COPY_PROBE_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.txt")
+
+
+def copy_probe():
+    """A plain device-to-device copy of COPY_PROBE_BYTES (reads and writes that
+    many bytes once): what FETCH_SIZE / WRITE_SIZE read for it scales the
+    counters to bytes."""
+    import torch
+    src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "launches": 3}), flush=True)
+    return 0
+
+
+def source_digest() -> str:
+    """Digest of the kernel sources: counters taken on other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_29785_amd", "csrc")
+    for name in sorted(os.listdir(base)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(base, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, batch: int):
+    """Calibrated HBM bytes per launch of `kernel` from the committed counter
+    summary, or None when it is absent, for another batch, or stale."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_digest") != source_digest() or kv.get("kernel") != kernel or int(kv.get("batch", -1)) != batch:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def kernel_bytes(kind: str, plan, batch: int, b: int) -> float:
@@ -74,6 +121,8 @@ def main():
         return 2
     if args.serving:
         return serving_main(args)
+    if args.copy_probe:
+        return copy_probe()
 
     import torch
     import paper_2603_29785_amd as qt
@@ -155,7 +204,8 @@ def main():
         k = kernels[dom]
         ach = k["achieved_GBs"]
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(dom, B) if args.precision == "fp32" else None,
                     "avg_launch_ms": round(k["avg_ms"], 4),
                     "bytes_per_launch": k["bytes"] / max(k["launches"], 1)}
 
@@ -206,6 +256,7 @@ def cpu_leg(args, plans, x_host, x_dev, B, W):
     done = 0
     errs_y, errs_x = [], []
     seg = 0
+    t_oracle = 0.0
     while True:
         i = (seg * 37) % B
         p, op = plans[seg % 3], ops[seg % 3]
@@ -216,7 +267,7 @@ def cpu_leg(args, plans, x_host, x_dev, B, W):
         Yo = op.forward(xi)
         xo = op.inverse(Yo)
         done += 1
-        t_oracle = time.perf_counter() - ta
+        t_oracle += time.perf_counter() - ta
         # the GPU's results on the same segment
         Yg = p.forward(x_dev[i:i + 1].contiguous())
         xg = p.inverse(Yg)
@@ -228,19 +279,11 @@ def cpu_leg(args, plans, x_host, x_dev, B, W):
         elapsed = time.perf_counter() - t0
         if elapsed >= args.cpu_seconds or seg >= 3 * B:
             break
-        _ = t_oracle
-    # time of the oracle only (the GPU calls above are excluded by re-timing)
-    t1 = time.perf_counter()
-    n_re = min(done, 3)
-    for s in range(n_re):
-        op = ops[s % 3]
-        xi = x_host[(s * 37) % B]
-        op.inverse(op.forward(xi))
-    per_seg = (time.perf_counter() - t1) / n_re
-    cpu_value = W["n"] / per_seg
+    # the oracle's own time only (the GPU calls on the same segments are not counted)
+    cpu_value = done * W["n"] / t_oracle
     cpu = {"value": cpu_value, "unit": "samples/s", "cores": 1, "kind": "oracle",
            "sample": "%d segments of %d samples (plans cycling Q=4/8/16), FP64 forward+inverse, "
-                     "single thread; rate from %d re-timed segments" % (done, W["n"], n_re),
+                     "single thread, %.1f s of oracle time" % (done, W["n"], t_oracle),
            "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
     return {"cpu_baseline": cpu,
             "recon_rel_err": {"coef_max": max(errs_y), "recon_max": max(errs_x), "segments": done,

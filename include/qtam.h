@@ -96,10 +96,23 @@ typedef struct {
   double p_floor_rel;       /* mask threshold relative to max P; default 1e-6     */
   int32_t precision;        /* qtam_precision                                     */
   int32_t flags;            /* QTAM_PLAN_HOST_ONLY or 0                           */
+  /* Composite bank (App. A, multi-Q / multi-window extension). n_planes = 0:
+   * one plane (q, window, window_param). n_planes >= 1: plane p uses
+   * plane_q[p], plane_window[p], plane_window_param[p] (host arrays, copied)
+   * and q / window / window_param are ignored. Every plane has the same
+   * n_rows-row frequency grid; the plan has n_planes * n_rows rows, plane
+   * after plane (row p * n_rows + k), and one frame P summed over all rows,
+   * so the inverse reconstructs from the whole bank.                        */
+  int32_t n_planes;
+  const double* plane_q;
+  const int32_t* plane_window;
+  const double* plane_window_param;
 } qtam_params;
 
 typedef struct {
-  int32_t n_rows;           /* R                                                  */
+  int32_t n_rows;           /* R = n_planes * rows_per_plane                      */
+  int32_t n_planes;         /* 1 for a plain plan                                 */
+  int32_t rows_per_plane;
   int32_t n_out;            /* N_out                                              */
   int32_t max_len;          /* max_k L_k = 2 h_k + 1                              */
   int32_t precision;
@@ -111,6 +124,7 @@ typedef struct {
   double masked_fraction;   /* fraction of bins 0..N/2 outside M                  */
   size_t workspace_bytes_per_segment;   /* max over forward / inverse / adjoints   */
   const double* freqs;      /* [R] nominal centre frequencies (Hz)                */
+  const double* row_q;      /* [R] quality factor of each row's plane             */
   const int32_t* centre;    /* [R] centre bins s_k                                */
   const int32_t* half_width;/* [R] h_k                                            */
   const int32_t* lo;        /* [R] first kept bin                                 */
@@ -159,6 +173,31 @@ qtam_status qtam_forward_adjoint(qtam_plan_t plan, const void* gy, void* gx, int
  * gy [batch, R, N_out] complex.                                              */
 qtam_status qtam_inverse_adjoint(qtam_plan_t plan, const void* gx, void* gy, int64_t batch,
                                  void* ws, size_t ws_bytes, qtam_stream_t stream);
+
+/* Plane metrics (the per-plane quality metric of the multi-Q extension,
+ * App. A): which statistic of a plane scores it.                           */
+typedef enum { QTAM_METRIC_ENERGY = 0,   /* sum over the plane's rows and m of |Y|^2 */
+               QTAM_METRIC_PEAK = 1      /* max over the plane's rows and m of |Y|^2 */
+} qtam_metric;
+
+/* qtam_forward that also returns row statistics: metric [batch, R] complex
+ * (float2 / double2, device) with metric[b, k] = (sum_m |Y_k[m]|^2,
+ * max_m |Y_k[m]|^2) of segment b. The statistics come from the coefficients
+ * while they are still on chip; y is written exactly as qtam_forward writes it. */
+qtam_status qtam_forward_metric(qtam_plan_t plan, const void* x, void* y, void* metric, int64_t batch,
+                                void* ws, size_t ws_bytes, qtam_stream_t stream);
+
+/* Optimal-plane selection, independently for each segment (multi-Q
+ * extension, App. A): score[b, p] is the energy (sum over the plane's rows of
+ * metric.x) or peak (max of metric.y) of plane p; best[b] is the first plane
+ * with the largest score; y_best[b] = y[b, best[b]*rows_per_plane ... +
+ * rows_per_plane - 1], a [batch, rows_per_plane, N_out] complex copy.
+ * y and metric as written by qtam_forward_metric; score (may be NULL) is
+ * [batch, n_planes] real in the plan precision, best [batch] int32; all device;
+ * y and y_best 16-byte aligned. A NaN score never wins.                     */
+qtam_status qtam_select_planes(qtam_plan_t plan, const void* y, const void* metric, int32_t kind,
+                               void* score, int32_t* best, void* y_best, int64_t batch,
+                               qtam_stream_t stream);
 
 /* Per-kernel timing with HIP events recorded on the call's own stream around
  * each launch. While enabled, every launch is bracketed by two events and the

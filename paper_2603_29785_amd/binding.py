@@ -21,6 +21,7 @@ CAP = {"cover": 0, "paper": 1, "none": 2, "manual": 3}
 NORM = {"unit_energy": 0, "paper_inv_energy": 1, "none": 2}
 WINDOW = {"bisquare": 0, "hann": 1, "kaiser": 2, "tukey": 3, "planck": 4}
 PLAN_HOST_ONLY = 1
+METRIC = {"energy": 0, "peak": 1}
 
 
 class QtamError(RuntimeError):
@@ -47,12 +48,18 @@ class c_params(ctypes.Structure):
         ("p_floor_rel", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("n_planes", ctypes.c_int32),
+        ("plane_q", ctypes.POINTER(ctypes.c_double)),
+        ("plane_window", ctypes.POINTER(ctypes.c_int32)),
+        ("plane_window_param", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
 class c_info(ctypes.Structure):
     _fields_ = [
         ("n_rows", ctypes.c_int32),
+        ("n_planes", ctypes.c_int32),
+        ("rows_per_plane", ctypes.c_int32),
         ("n_out", ctypes.c_int32),
         ("max_len", ctypes.c_int32),
         ("precision", ctypes.c_int32),
@@ -65,6 +72,7 @@ class c_info(ctypes.Structure):
         ("masked_fraction", ctypes.c_double),
         ("workspace_bytes_per_segment", ctypes.c_size_t),
         ("freqs", ctypes.POINTER(ctypes.c_double)),
+        ("row_q", ctypes.POINTER(ctypes.c_double)),
         ("centre", ctypes.POINTER(ctypes.c_int32)),
         ("half_width", ctypes.POINTER(ctypes.c_int32)),
         ("lo", ctypes.POINTER(ctypes.c_int32)),
@@ -79,7 +87,7 @@ class c_info(ctypes.Structure):
 EXPORTED = [
     "qtam_plan_create", "qtam_plan_info", "qtam_plan_destroy", "qtam_workspace_size",
     "qtam_forward", "qtam_inverse", "qtam_forward_adjoint", "qtam_inverse_adjoint",
-    "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string", "qtam_version",
+    "qtam_forward_metric", "qtam_select_planes", "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string", "qtam_version",
 ]
 
 
@@ -100,6 +108,10 @@ def _load():
         f = getattr(L, name)
         f.argtypes = [vp, vp, vp, i64, vp, sz, vp]
         f.restype = ctypes.c_int
+    L.qtam_forward_metric.argtypes = [vp, vp, vp, vp, i64, vp, sz, vp]
+    L.qtam_forward_metric.restype = ctypes.c_int
+    L.qtam_select_planes.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, i64, vp]
+    L.qtam_select_planes.restype = ctypes.c_int
     L.qtam_timing_enable.argtypes = [vp, ctypes.c_int32]
     L.qtam_timing_enable.restype = ctypes.c_int
     L.qtam_timing_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
@@ -138,6 +150,8 @@ def _arr(ptr, n, dtype):
 @dataclass(frozen=True)
 class PlanInfo:
     n_rows: int
+    n_planes: int
+    rows_per_plane: int
     n_out: int
     max_len: int
     precision: int
@@ -159,7 +173,10 @@ class Plan:
                  f_max: float = 0.0, n_rows: int = 0, freqs=None, window: str = "bisquare",
                  window_param: float = 0.0, cap_mode: str = "cover", max_window: int = 0,
                  norm_mode: str = "unit_energy", n_out: int = 0, p_floor_rel: float = 1e-6,
-                 precision: str = "fp32", host_only: bool = False):
+                 precision: str = "fp32", host_only: bool = False, planes=None):
+        """planes: optional list of (q, window, window_param) for a composite
+        bank (rows plane after plane, one shared frame); q, window and
+        window_param are then ignored."""
         self._h = ctypes.c_void_p()
         p = c_params()
         p.sample_rate = float(sample_rate)
@@ -183,18 +200,28 @@ class Plan:
         p.p_floor_rel = float(p_floor_rel)
         p.precision = FP64 if precision in ("fp64", FP64, "float64") else FP32
         p.flags = PLAN_HOST_ONLY if host_only else 0
+        if planes:
+            self._pq = np.array([float(t[0]) for t in planes], dtype=np.float64)
+            self._pw = np.array([WINDOW[t[1]] if isinstance(t[1], str) else int(t[1]) for t in planes],
+                                dtype=np.int32)
+            self._pp = np.array([float(t[2]) for t in planes], dtype=np.float64)
+            p.n_planes = len(planes)
+            p.plane_q = self._pq.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            p.plane_window = self._pw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            p.plane_window_param = self._pp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.params = dict(sample_rate=sample_rate, n_samples=n_samples, q=q, f_min=f_min, f_max=f_max,
                            n_rows=p.n_rows, window=window, window_param=window_param, cap_mode=cap_mode,
                            max_window=max_window, norm_mode=norm_mode, n_out=n_out,
-                           p_floor_rel=p_floor_rel, precision=precision)
+                           p_floor_rel=p_floor_rel, precision=precision, planes=planes)
         _check(lib.qtam_plan_create(ctypes.byref(p), ctypes.byref(self._h)), "qtam_plan_create")
         ci = c_info()
         _check(lib.qtam_plan_info(self._h, ctypes.byref(ci)), "qtam_plan_info")
-        self.info = PlanInfo(ci.n_rows, ci.n_out, ci.max_len, ci.precision, ci.n_samples, ci.n_bins,
+        self.info = PlanInfo(ci.n_rows, ci.n_planes, ci.rows_per_plane, ci.n_out, ci.max_len, ci.precision, ci.n_samples, ci.n_bins,
                              ci.sum_len, ci.l_max, ci.frame_A, ci.frame_B, ci.masked_fraction,
                              ci.workspace_bytes_per_segment)
         R, nb, sl = ci.n_rows, ci.n_bins, ci.sum_len
         self.freqs = _arr(ci.freqs, R, np.float64)
+        self.row_q = _arr(ci.row_q, R, np.float64)
         self.centre = _arr(ci.centre, R, np.int64)
         self.half_width = _arr(ci.half_width, R, np.int64)
         self.lo = _arr(ci.lo, R, np.int64)
@@ -224,6 +251,14 @@ class Plan:
     @property
     def N_out(self) -> int:
         return self.info.n_out
+
+    @property
+    def planes(self) -> int:
+        return self.info.n_planes
+
+    @property
+    def rows_per_plane(self) -> int:
+        return self.info.rows_per_plane
 
     @property
     def fp64(self) -> bool:
@@ -299,6 +334,50 @@ class Plan:
                                                     dtype=self._complex_dtype(), device=x.device)
         self._call(lib.qtam_forward, "qtam_forward", x, y, batch, ws, stream)
         return y
+
+    def forward_metric(self, x, out=None, metric=None, ws=None, stream=None):
+        """Forward plus per-row statistics: (Y, metric) with metric [..., R]
+        complex holding (sum_m |Y_k[m]|^2, max_m |Y_k[m]|^2) of each row."""
+        torch = self._torch()
+        x = self._check_signal(x)
+        lead = x.shape[:-1]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        y = out if out is not None else torch.empty(tuple(lead) + (self.R, self.N_out),
+                                                    dtype=self._complex_dtype(), device=x.device)
+        m = metric if metric is not None else torch.empty(tuple(lead) + (self.R,), dtype=self._complex_dtype(),
+                                                          device=x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        ws = self._workspace(batch, x.device, ws)
+        _check(lib.qtam_forward_metric(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                       ctypes.c_void_p(m.data_ptr()), int(batch),
+                                       ctypes.c_void_p(ws.data_ptr()),
+                                       ctypes.c_size_t(ws.numel() * ws.element_size()),
+                                       ctypes.c_void_p(stream.cuda_stream)), "qtam_forward_metric")
+        return y, m
+
+    def select_planes(self, y, metric, kind="energy", stream=None):
+        """Optimal plane per segment: (score [..., planes], best [...] int32,
+        y_best [..., rows_per_plane, N_out])."""
+        torch = self._torch()
+        y = self._check_rows(y)
+        lead = y.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        if metric.dtype != self._complex_dtype() or tuple(metric.shape) != tuple(lead) + (self.R,):
+            raise ValueError("metric must be complex [..., R] as forward_metric returns it")
+        metric = metric.contiguous()
+        score = torch.empty(tuple(lead) + (self.planes,), dtype=self._real_dtype(), device=y.device)
+        best = torch.empty(tuple(lead), dtype=torch.int32, device=y.device)
+        yb = torch.empty(tuple(lead) + (self.rows_per_plane, self.N_out), dtype=self._complex_dtype(),
+                         device=y.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(y.device)
+        k = METRIC[kind] if isinstance(kind, str) else int(kind)
+        _check(lib.qtam_select_planes(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(metric.data_ptr()),
+                                      k, ctypes.c_void_p(score.data_ptr()), ctypes.c_void_p(best.data_ptr()),
+                                      ctypes.c_void_p(yb.data_ptr()), int(batch),
+                                      ctypes.c_void_p(stream.cuda_stream)), "qtam_select_planes")
+        return score, best, yb
 
     def inverse(self, y, out=None, ws=None, stream=None):
         """Y [..., R, N_out] complex -> x [..., N] real (canonical dual frame)."""

@@ -212,6 +212,48 @@ __device__ __forceinline__ int xcd_major_block(int nblocks) {
 // their baseband slots (c - s_k) mod N_out (roll to baseband, crop, zero pad),
 // the N_out-point inverse FFT runs in registers and LDS, and the envelope row
 // is stored. One unit of G consecutive rows per workgroup.
+// Row statistics (sum and max of |Y|^2 over the row) of the E values each of
+// a row's TPR threads holds. Lanes of one row inside a wave combine by an xor
+// butterfly (every lane ends with the same bits); rows spanning several waves
+// then add the per-wave results in wave order through LDS. Every thread of the
+// block must call it.
+template <typename T, int E, int TPR, int NT>
+__device__ __forceinline__ void row_stats(const typename Complex<T>::type (&v)[E], int tl, bool ok,
+                                          typename Complex<T>::type* __restrict__ dst) {
+  using C = typename Complex<T>::type;
+  constexpr int W = TPR < 64 ? TPR : 64;     // lanes of a row within one wave
+  constexpr int WPR = TPR > 64 ? TPR / 64 : 1;
+  T e = 0, m = 0;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const T a = v[i].x * v[i].x + v[i].y * v[i].y;
+    e += a;
+    m = fmax(m, a);
+  }
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) {
+    e += __shfl_xor(e, o, W);
+    m = fmax(m, __shfl_xor(m, o, W));
+  }
+  if constexpr (WPR == 1) {
+    if (ok && tl == 0) *dst = C{e, m};
+  } else {
+    __shared__ C part[NT / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = C{e, m};
+    __syncthreads();
+    if (ok && tl == 0) {
+      const C* pr = part + (threadIdx.x >> 6);
+      C r = pr[0];
+#pragma unroll
+      for (int w = 1; w < WPR; ++w) {
+        r.x += pr[w].x;
+        r.y = fmax(r.y, pr[w].y);
+      }
+      *dst = r;
+    }
+  }
+}
+
 // When a wave holds one row (TPR >= 64) and the row touches neither DC nor
 // Nyquist, buffer resources scoped to the row's kept support do the cropping:
 // slots outside it fall outside the resources and read 0, with no test.
@@ -222,7 +264,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ Y,
     const RowMeta* __restrict__ rows, const typename Complex<T>::type* __restrict__ roww,
     const T* __restrict__ tab, int R, int total, int half, int sum_len, int64_t spec_elems,
-    const typename Complex<T>::type* __restrict__ tw, int nblocks) {
+    const typename Complex<T>::type* __restrict__ tw, int nblocks, typename Complex<T>::type* __restrict__ stats) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, +1, TW_POW>;
@@ -296,6 +338,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
   const uint32_t vb = static_cast<uint32_t>(g * L + tl) * sizeof(C);
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) bstore<C>(ry, v[i], vb, F::out_off(i) * sizeof(C));
+  if (stats != nullptr) row_stats<T, Geo::E, Geo::TPR, Geo::NT>(v, tl, ok, stats + gr);
 }
 
 // Inverse rows: N_out-point FFT of each envelope row; the kept slots times the
@@ -487,6 +530,84 @@ __global__ __launch_bounds__(256) void k_ola(
   if (p > 0 && q != p) Zs[q] = c_add(c_add(B, Ac), c_mul_si<-1>(c_mul(c_conj(w), c_sub(B, Ac))));
 }
 
+// Row statistics read back from Y (rows too long for one workgroup): one
+// workgroup per row, fixed-order partial sums and a fixed tree.
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_stats(const typename Complex<T>::type* __restrict__ Y,
+                                                   typename Complex<T>::type* __restrict__ stats, int64_t n_out) {
+  using C = typename Complex<T>::type;
+  __shared__ T se[256], sm[256];
+  const C* row = Y + int64_t(blockIdx.x) * n_out;
+  T e = 0, m = 0;
+  for (int64_t i = threadIdx.x; i < n_out; i += 256) {
+    const C v = row[i];
+    const T a = v.x * v.x + v.y * v.y;
+    e += a;
+    m = fmax(m, a);
+  }
+  se[threadIdx.x] = e;
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      se[threadIdx.x] += se[threadIdx.x + w];
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) stats[blockIdx.x] = C{se[0], sm[0]};
+}
+
+// Plane scores and the best plane of each segment (one workgroup per
+// segment): energy sums a plane's row energies, peak takes their maximum; the
+// first plane with the largest score wins and a NaN score never does.
+template <typename T>
+__global__ __launch_bounds__(256) void k_plane_best(const typename Complex<T>::type* __restrict__ stats,
+                                                    int rows_per_plane, int planes, int peak,
+                                                    T* __restrict__ score, int* __restrict__ best) {
+  using C = typename Complex<T>::type;
+  __shared__ T red[256];
+  const int64_t seg = blockIdx.x;
+  const C* st = stats + seg * int64_t(rows_per_plane) * planes;
+  T top = 0;
+  int arg = -1;
+  for (int p = 0; p < planes; ++p) {
+    T a = 0;
+    for (int k = threadIdx.x; k < rows_per_plane; k += 256) {
+      const C v = st[int64_t(p) * rows_per_plane + k];
+      a = peak ? fmax(a, v.y) : a + v.x;
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (int(threadIdx.x) < w)
+        red[threadIdx.x] = peak ? fmax(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
+      __syncthreads();
+    }
+    const T sc = red[0];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (score != nullptr) score[seg * planes + p] = sc;
+      if (sc == sc && (arg < 0 || sc > top)) {
+        top = sc;
+        arg = p;
+      }
+    }
+  }
+  if (threadIdx.x == 0) best[seg] = arg < 0 ? 0 : arg;
+}
+
+// y_best[seg] = plane best[seg] of y[seg], copied in 16-byte units.
+__global__ __launch_bounds__(256) void k_gather_plane(const uint4* __restrict__ y, const int* __restrict__ best,
+                                                      uint4* __restrict__ out, int64_t plane_units, int planes) {
+  const int64_t seg = blockIdx.y;
+  const int b = best[seg];
+  const uint4* src = y + (seg * planes + b) * plane_units;
+  uint4* dst = out + seg * plane_units;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < plane_units; i += int64_t(gridDim.x) * 256)
+    dst[i] = src[i];
+}
+
 }  // namespace qtam
 
 // ===========================================================================
@@ -497,11 +618,12 @@ using namespace qtam;
 namespace {
 
 enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_TWIST, K_FWD_ROWS, K_FWD_ROWS2, K_INV_ROWS, K_INV_ROWS2, K_OLA,
-            K_SYN, K_SYN1, K_SYN2, K_NUM };
+            K_SYN, K_SYN1, K_SYN2, K_ROW_STATS, K_PLANE_BEST, K_GATHER, K_NUM };
 const char* const kKindName[K_NUM] = {"spectrum_fft", "spectrum_fft_pass1", "spectrum_fft_pass2",
                                        "spectrum_twist", "fwd_rows", "fwd_rows_pass2", "inv_rows",
                                        "inv_rows_pass2", "overlap_add", "synthesis_fft",
-                                       "synthesis_fft_pass1", "synthesis_fft_pass2"};
+                                       "synthesis_fft_pass1", "synthesis_fft_pass2", "row_stats",
+                                       "plane_best", "gather_plane"};
 
 enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3 };
 
@@ -828,7 +950,7 @@ bool launch_fft_rows_t(int log2l, const void* in, void* out, int64_t n2, int64_t
 template <typename T>
 bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* out, const RowMeta* rows,
                  const void* roww, const void* tab, int R, int64_t total_rows, int64_t half, int64_t sum_len,
-                 const void* tw, hipStream_t st) {
+                 const void* tw, hipStream_t st, void* stats = nullptr) {
   using C = typename Complex<T>::type;
   switch (log2l) {
 #define X(LG)                                                                                          \
@@ -841,7 +963,8 @@ bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* o
         hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(Geo::NT), 0, st, static_cast<const C*>(in), \
                            static_cast<C*>(out), rows, static_cast<const C*>(roww),                    \
                            static_cast<const T*>(tab), R, int(total_rows), int(half), int(sum_len),    \
-                           (total_rows / R) * half, static_cast<const C*>(tw), blocks);                \
+                           (total_rows / R) * half, static_cast<const C*>(tw), blocks,                 \
+                           static_cast<C*>(stats));                                                    \
       } else {                                                                                         \
         hipLaunchKernelGGL((k_inv_rows<T, (1 << LG)>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st,   \
                            static_cast<const C*>(in), static_cast<C*>(out), rows,                      \
@@ -964,7 +1087,7 @@ Twiddle2<typename Complex<T>::type> tw2_of(const qtam_plan_s* pl) {
 // analysis: real signal x -> rows (forward with T_FWD, inverse adjoint with T_AINV)
 template <typename T>
 bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t segs, char* ws,
-                  const WsLayout& lay, hipStream_t st) {
+                  const WsLayout& lay, hipStream_t st, void* stats) {
   const HostPlan& hp = pl->hp;
   const int64_t half = hp.half;
   void* spec = ws + lay.spec;
@@ -1001,13 +1124,22 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
                                    segs * hp.rows, half, hp.n_out, pl->r1, pl->d_tw_r2, twr, st))
         return false;
     }
-    Timed tm(pl, K_FWD_ROWS2, st);
-    return launch_fft_rows_t<T, +1>(ilog2(pl->r1), A, y, pl->r2, segs * hp.rows, hp.n_out, pl->d_tw_r1, st);
+    {
+      Timed tm(pl, K_FWD_ROWS2, st);
+      if (!launch_fft_rows_t<T, +1>(ilog2(pl->r1), A, y, pl->r2, segs * hp.rows, hp.n_out, pl->d_tw_r1, st))
+        return false;
+    }
+    if (stats) {
+      Timed tm(pl, K_ROW_STATS, st);
+      hipLaunchKernelGGL((k_row_stats<T>), dim3(unsigned(segs * hp.rows)), dim3(256), 0, st, static_cast<const C*>(y),
+                         static_cast<C*>(stats), int64_t(hp.n_out));
+    }
+    return true;
   }
   Timed tm(pl, K_FWD_ROWS, st);
   return launch_rows<T>(true, table == T_FWD && pl->analytic_fwd, ilog2(hp.n_out), spec, y, pl->d_rows,
                         pl->d_roww, pl->d_tab[table], hp.rows, segs * hp.rows, half, hp.sum_len,
-                        pl->d_tw_out, st);
+                        pl->d_tw_out, st, stats);
 }
 
 // synthesis: rows -> real signal (inverse with T_DUAL, forward adjoint with T_AFWD)
@@ -1063,7 +1195,7 @@ bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t s
 enum Op { OP_FORWARD, OP_INVERSE, OP_FWD_ADJ, OP_INV_ADJ };
 
 qtam_status run_op(qtam_plan_t pl, Op op, const void* in, void* out, int64_t batch, void* ws, size_t ws_bytes,
-                   qtam_stream_t stream) {
+                   qtam_stream_t stream, void* stats = nullptr) {
   if (!pl || batch < 0) return QTAM_ERR_INVALID_ARG;
   if (batch == 0) return QTAM_OK;
   if (!in || !out || !ws) return QTAM_ERR_INVALID_ARG;
@@ -1086,9 +1218,10 @@ qtam_status run_op(qtam_plan_t pl, Op op, const void* in, void* out, int64_t bat
     const char* src = static_cast<const char*>(in) + size_t(b0) * (analysis ? x_seg : y_seg);
     char* dst = static_cast<char*>(out) + size_t(b0) * (analysis ? y_seg : x_seg);
     bool ok;
+    void* chunk_stats = stats ? static_cast<char*>(stats) + size_t(b0) * size_t(hp.rows) * 2 * rb : nullptr;
     if (analysis)
-      ok = f64 ? run_analysis<double>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st)
-               : run_analysis<float>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st);
+      ok = f64 ? run_analysis<double>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st, chunk_stats)
+               : run_analysis<float>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st, chunk_stats);
     else
       ok = f64 ? run_synthesis<double>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st)
                : run_synthesis<float>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st);
@@ -1175,7 +1308,7 @@ qtam_status qtam_plan_create(const qtam_params* params, qtam_plan_t* out) {
       (void)hipGetLastError();
       pl->num_cus = 1;
     }
-    pl->analytic_fwd = pl->hp.window == QTAM_WIN_BISQUARE;
+    pl->analytic_fwd = pl->hp.all_bisquare;
     st = pl->hp.precision == QTAM_FP64 ? upload<double>(pl) : upload<float>(pl);
     if (st != QTAM_OK) {
       if (pl->dmem) (void)hipFree(pl->dmem);
@@ -1192,6 +1325,9 @@ qtam_status qtam_plan_info(qtam_plan_t pl, qtam_plan_info_t* info) {
   if (!pl || !info) return QTAM_ERR_INVALID_ARG;
   const HostPlan& hp = pl->hp;
   info->n_rows = hp.rows;
+  info->n_planes = hp.planes;
+  info->rows_per_plane = hp.rows_per_plane;
+  info->row_q = hp.row_q.data();
   info->n_out = hp.n_out;
   info->max_len = hp.max_len;
   info->precision = hp.precision;
@@ -1234,6 +1370,52 @@ size_t qtam_workspace_size(qtam_plan_t pl, int64_t batch) {
 qtam_status qtam_forward(qtam_plan_t pl, const void* x, void* y, int64_t batch, void* ws, size_t ws_bytes,
                          qtam_stream_t stream) {
   return run_op(pl, OP_FORWARD, x, y, batch, ws, ws_bytes, stream);
+}
+
+qtam_status qtam_forward_metric(qtam_plan_t pl, const void* x, void* y, void* metric, int64_t batch, void* ws,
+                                size_t ws_bytes, qtam_stream_t stream) {
+  if (batch > 0 && !metric) return QTAM_ERR_INVALID_ARG;
+  return run_op(pl, OP_FORWARD, x, y, batch, ws, ws_bytes, stream, metric);
+}
+
+qtam_status qtam_select_planes(qtam_plan_t pl, const void* y, const void* metric, int32_t kind, void* score,
+                               int32_t* best, void* y_best, int64_t batch, qtam_stream_t stream) {
+  if (!pl || batch < 0 || (kind != QTAM_METRIC_ENERGY && kind != QTAM_METRIC_PEAK)) return QTAM_ERR_INVALID_ARG;
+  if (batch == 0) return QTAM_OK;
+  if (!y || !metric || !best || !y_best) return QTAM_ERR_INVALID_ARG;
+  if (!pl->gpu_supported) return pl->unsupported_reason;
+  if (!pl->device) return QTAM_ERR_INVALID_ARG;
+  const HostPlan& hp = pl->hp;
+  const bool f64 = hp.precision == QTAM_FP64;
+  const size_t cb = f64 ? 16 : 8;
+  const int64_t units = int64_t(hp.rows_per_plane) * hp.n_out * int64_t(cb) / 16;
+  const int64_t gx = std::min<int64_t>((units + 255) / 256, 1024);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  for (int64_t b0 = 0; b0 < batch; b0 += 65535) {
+    const int64_t segs = std::min<int64_t>(65535, batch - b0);
+    const char* ys = static_cast<const char*>(y) + size_t(b0) * size_t(hp.rows) * size_t(hp.n_out) * cb;
+    const char* ms = static_cast<const char*>(metric) + size_t(b0) * size_t(hp.rows) * cb;
+    char* sc = score ? static_cast<char*>(score) + size_t(b0) * size_t(hp.planes) * cb / 2 : nullptr;
+    {
+      Timed tm(pl, K_PLANE_BEST, st);
+      if (f64)
+        hipLaunchKernelGGL((k_plane_best<double>), dim3(unsigned(segs)), dim3(256), 0, st,
+                           reinterpret_cast<const double2*>(ms), hp.rows_per_plane, hp.planes,
+                           int(kind == QTAM_METRIC_PEAK), reinterpret_cast<double*>(sc), best + b0);
+      else
+        hipLaunchKernelGGL((k_plane_best<float>), dim3(unsigned(segs)), dim3(256), 0, st,
+                           reinterpret_cast<const float2*>(ms), hp.rows_per_plane, hp.planes,
+                           int(kind == QTAM_METRIC_PEAK), reinterpret_cast<float*>(sc), best + b0);
+    }
+    Timed tm(pl, K_GATHER, st);
+    hipLaunchKernelGGL(k_gather_plane, dim3(unsigned(gx), unsigned(segs)), dim3(256), 0, st,
+                       reinterpret_cast<const uint4*>(ys), best + b0,
+                       reinterpret_cast<uint4*>(static_cast<char*>(y_best) + size_t(b0) * size_t(units) * 16), units,
+                       hp.planes);
+    if (hipGetLastError() != hipSuccess) return QTAM_ERR_DEVICE;
+  }
+  return QTAM_OK;
 }
 
 qtam_status qtam_inverse(qtam_plan_t pl, const void* y, void* x, int64_t batch, void* ws, size_t ws_bytes,

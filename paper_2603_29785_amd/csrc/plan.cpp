@@ -60,26 +60,47 @@ int64_t pow2_at_least(int64_t v) {
 
 qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
   const int64_t n = p.n_samples;
-  if (!(p.sample_rate > 0.0) || n < 16 || (n & 1) || !(p.q > 0.0) || p.n_rows < 1)
+  if (!(p.sample_rate > 0.0) || n < 16 || (n & 1) || p.n_rows < 1 || p.n_planes < 0)
     return QTAM_ERR_INVALID_ARG;
-  if (p.window < QTAM_WIN_BISQUARE || p.window > QTAM_WIN_PLANCK) return QTAM_ERR_INVALID_ARG;
+  // planes of the bank: (Q, window, parameter)
+  struct Plane {
+    double q;
+    int32_t window;
+    double param;
+  };
+  std::vector<Plane> planes;
+  if (p.n_planes == 0) {
+    planes.push_back(Plane{p.q, p.window, p.window_param});
+  } else {
+    if (!p.plane_q || !p.plane_window || !p.plane_window_param) return QTAM_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < p.n_planes; ++i)
+      planes.push_back(Plane{p.plane_q[i], p.plane_window[i], p.plane_window_param[i]});
+  }
+  if (int64_t(planes.size()) * p.n_rows > std::numeric_limits<int32_t>::max()) return QTAM_ERR_INVALID_ARG;
+  for (const Plane& pl : planes) {
+    if (!(pl.q > 0.0)) return QTAM_ERR_INVALID_ARG;
+    if (pl.window < QTAM_WIN_BISQUARE || pl.window > QTAM_WIN_PLANCK) return QTAM_ERR_INVALID_ARG;
+  }
   if (p.precision != QTAM_FP32 && p.precision != QTAM_FP64) return QTAM_ERR_INVALID_ARG;
   if (p.n_out < 0 || !(p.p_floor_rel >= 0.0) || p.p_floor_rel > 1.0) return QTAM_ERR_INVALID_ARG;
 
   hp = HostPlan();
   hp.fs = p.sample_rate;
-  hp.q = p.q;
+  hp.q = planes[0].q;
   hp.f_min = p.f_min;
   hp.f_max = p.f_max;
   hp.p_floor_rel = p.p_floor_rel;
-  hp.window = p.window;
-  hp.window_param = p.window_param;
+  hp.window = planes[0].window;
+  hp.window_param = planes[0].param;
+  for (const Plane& pl : planes) hp.all_bisquare = hp.all_bisquare && pl.window == QTAM_WIN_BISQUARE;
   hp.n = n;
   hp.half = n / 2;
   hp.n_bins = n / 2 + 1;
-  hp.rows = p.n_rows;
+  hp.planes = static_cast<int32_t>(planes.size());
+  hp.rows_per_plane = p.n_rows;
+  hp.rows = hp.planes * p.n_rows;
   hp.precision = p.precision;
-  const int32_t R = p.n_rows;
+  const int32_t R = p.n_rows;      // rows of one plane
   const double T = static_cast<double>(n) / p.sample_rate;
 
   // Frequency grid.
@@ -117,17 +138,23 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
     default: return QTAM_ERR_INVALID_ARG;
   }
 
-  // Rows: centre, width, kept support, packed window.
-  hp.centre.resize(R);
-  hp.half_width.resize(R);
-  hp.lo.resize(R);
-  hp.hi.resize(R);
-  hp.offset.resize(R);
+  // Rows of every plane: centre, width, kept support, packed window.
+  const int32_t RT = hp.rows;
+  hp.freq.resize(RT);
+  for (int32_t k = R; k < RT; ++k) hp.freq[k] = hp.freq[k % R];
+  hp.row_q.resize(RT);
+  hp.centre.resize(RT);
+  hp.half_width.resize(RT);
+  hp.lo.resize(RT);
+  hp.hi.resize(RT);
+  hp.offset.resize(RT);
   int64_t longest = 0;
-  for (int32_t k = 0; k < R; ++k) {
+  for (int32_t k = 0; k < RT; ++k) {
+    const Plane& plane = planes[k / R];
+    hp.row_q[k] = plane.q;
     const double f = hp.freq[k];
     const int64_t s = static_cast<int64_t>(std::floor(f * T + 0.5));
-    int64_t h = std::max<int64_t>(1, static_cast<int64_t>(std::ceil(f * T / p.q)) / 2);
+    int64_t h = std::max<int64_t>(1, static_cast<int64_t>(std::ceil(f * T / plane.q)) / 2);
     if (hp.l_max > 0) h = std::max<int64_t>(1, std::min<int64_t>(h, hp.l_max / 2));
     const int64_t a = std::max<int64_t>(0, s - h), b = std::min<int64_t>(hp.half, s + h);
     if (a > b || h > std::numeric_limits<int32_t>::max() / 4) return QTAM_ERR_INVALID_ARG;
@@ -142,7 +169,7 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
     double e2 = 0.0;
     const size_t base = hp.win.size();
     for (int64_t c = a; c <= b; ++c) {
-      const double w = shape(p.window, static_cast<double>(c - s) / static_cast<double>(h), p.window_param);
+      const double w = shape(plane.window, static_cast<double>(c - s) / static_cast<double>(h), plane.param);
       hp.win.push_back(w);
       e2 += w * w;
     }
@@ -169,9 +196,9 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
 
   // Frame operator, mask, covering rows per bin.
   hp.P.assign(hp.n_bins, 0.0);
-  hp.bin_klo.assign(hp.n_bins, R);
+  hp.bin_klo.assign(hp.n_bins, RT);
   hp.bin_khi.assign(hp.n_bins, -1);
-  for (int32_t k = 0; k < R; ++k)
+  for (int32_t k = 0; k < RT; ++k)
     for (int64_t c = hp.lo[k]; c <= hp.hi[k]; ++c) {
       const double w = hp.win[hp.offset[k] + (c - hp.lo[k])];
       hp.P[c] += w * w;
@@ -205,7 +232,7 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
   hp.dual_tab.resize(hp.sum_len);
   hp.afwd_tab.resize(hp.sum_len);
   hp.ainv_tab.resize(hp.sum_len);
-  for (int32_t k = 0; k < R; ++k)
+  for (int32_t k = 0; k < RT; ++k)
     for (int64_t c = hp.lo[k]; c <= hp.hi[k]; ++c) {
       const int64_t e = hp.offset[k] + (c - hp.lo[k]);
       const double w = hp.win[e];

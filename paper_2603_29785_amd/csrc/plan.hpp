@@ -15,7 +15,10 @@ struct HostPlan {
   int64_t n = 0;            // N samples per segment
   int64_t half = 0;         // N/2
   int64_t n_bins = 0;       // N/2 + 1
-  int32_t rows = 0;         // R
+  int32_t rows = 0;         // R, all planes
+  int32_t planes = 1;       // planes of a composite bank
+  int32_t rows_per_plane = 0;
+  bool all_bisquare = true; // every plane uses the bisquare window
   int32_t n_out = 0;        // N_out
   int32_t max_len = 0;      // max 2 h_k + 1
   int32_t precision = QTAM_FP32;
@@ -24,7 +27,7 @@ struct HostPlan {
   int64_t sum_len = 0;      // sum of kept support lengths
 
   // per row
-  std::vector<double> freq;
+  std::vector<double> freq, row_q;
   std::vector<int32_t> centre, half_width, lo, hi;
   std::vector<int64_t> offset;
 

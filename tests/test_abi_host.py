@@ -148,3 +148,37 @@ def test_non_power_of_two_reports_unsupported_not_invalid():
     dummy = ctypes.c_void_p(0x1000)
     st_ = binding.lib.qtam_forward(gp._h, dummy, dummy, 1, dummy, 1 << 30, None)
     assert st_ == binding.QTAM_ERR_UNSUPPORTED
+
+
+COMPOSITES = [
+    [(4.0, "bisquare", 0.0), (8.0, "bisquare", 0.0), (16.0, "bisquare", 0.0)],
+    [(3.0, "hann", 0.0), (9.0, "kaiser", 6.0), (27.0, "tukey", 0.4), (12.0, "planck", 0.3)],
+]
+
+
+@pytest.mark.parametrize("planes", COMPOSITES)
+def test_composite_plan_tables_match_oracle(planes):
+    kw = dict(sample_rate=4096.0, n_samples=32768, q=1.0, f_min=16.0, f_max=1800.0, n_rows=40)
+    gp = host_plan(planes=planes, **kw)
+    op = o.OraclePlan(fs=4096.0, n=32768, q=1.0, f_min=16.0, f_max=1800.0, rows=40,
+                      planes=[(q, WINS[w], a) for q, w, a in planes])
+    assert gp.planes == len(planes) and gp.rows_per_plane == 40 and gp.R == 40 * len(planes)
+    assert np.array_equal(gp.row_q, np.repeat([q for q, _, _ in planes], 40))
+    compare_tables(gp, op)
+
+
+def test_composite_invalid_and_select_without_device():
+    with pytest.raises(qt.QtamError):
+        host_plan(sample_rate=1024.0, n_samples=4096, q=1.0, f_min=10.0, f_max=400.0, n_rows=16,
+                  planes=[(4.0, "bisquare", 0.0), (-2.0, "bisquare", 0.0)])
+    gp = host_plan(sample_rate=1024.0, n_samples=4096, q=1.0, f_min=10.0, f_max=400.0, n_rows=16,
+                   planes=[(4.0, "bisquare", 0.0), (8.0, "bisquare", 0.0)])
+    L = binding.lib
+    d = ctypes.c_void_p(0x1000)
+    ws = gp.workspace_bytes(1)
+    assert L.qtam_forward_metric(gp._h, d, d, None, 1, d, ws, None) == binding.QTAM_ERR_INVALID_ARG
+    assert L.qtam_forward_metric(gp._h, d, d, d, 1, d, ws, None) == binding.QTAM_ERR_INVALID_ARG
+    assert L.qtam_select_planes(gp._h, d, d, 7, d, d, d, 1, None) == binding.QTAM_ERR_INVALID_ARG
+    assert L.qtam_select_planes(gp._h, d, d, 0, d, None, d, 1, None) == binding.QTAM_ERR_INVALID_ARG
+    assert L.qtam_select_planes(gp._h, d, d, 0, d, d, d, 1, None) == binding.QTAM_ERR_INVALID_ARG  # host-only
+    assert L.qtam_select_planes(gp._h, d, d, 1, None, d, d, 0, None) == binding.QTAM_OK

@@ -231,3 +231,33 @@ def test_long_rows_parity(torch_dev, case):
         assert rel(Y[b], Yr) <= TOL[precision], b
         xo = op.inverse(Yr)
         assert rel(xr[b], xo) <= TOL[precision] * (10 if precision == "fp32" else 1), b
+
+
+@pytest.mark.parametrize("window,param", [("hann", 0.0), ("kaiser", 6.0), ("tukey", 0.5), ("planck", 0.3)])
+def test_window_family_parity(torch_dev, window, param):
+    """Non-bisquare windows (App. A) take the table-weight path."""
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    wi = {"hann": o.WIN_HANN, "kaiser": o.WIN_KAISER, "tukey": o.WIN_TUKEY, "planck": o.WIN_PLANCK}[window]
+    for precision in ("fp32", "fp64"):
+        gp = qt.Plan(4096.0, 32768, 8.0, 20.0, 2000.0, 96, window=window, window_param=param, precision=precision)
+        op = o.OraclePlan(fs=4096.0, n=32768, q=8.0, f_min=20.0, f_max=2000.0, rows=96, window=wi, window_param=param)
+        x = host_input(synthetic.batched_segments(2, 32768, 4096.0, workload=13, dtype=np.float64), precision)
+        Y = gp.forward(to_dev(torch, x, precision))
+        assert rel(Y.cpu().numpy(), op.forward(x)) <= TOL[precision]
+        assert rel(gp.inverse(Y).cpu().numpy(), op.project(x)) <= TOL[precision] * 10
+
+
+def test_masked_coefficients_inverse(torch_dev):
+    """Inverting a masked coefficient set (keep only the strongest rows) is the
+    canonical-dual synthesis of the masked set, as in the oracle."""
+    torch = torch_dev
+    gp, op = plans(4096.0, 16384, 8.0, 20.0, 1000.0, 64, "fp64")
+    x = synthetic.single_segment()
+    Y = op.forward(x)
+    keep = np.zeros_like(Y)
+    top = np.argsort(np.abs(Y).max(axis=1))[-8:]
+    keep[top] = Y[top]
+    keep[:, 100:200] = 0
+    xr = gp.inverse(torch.from_numpy(keep).cuda()).cpu().numpy()
+    assert rel(xr, op.inverse(keep)) <= 1e-12
