@@ -45,13 +45,14 @@ def parse():
     ap.add_argument("--duration", type=float, default=30.0, help="serving: seconds of arrivals")
     ap.add_argument("--hbm-budget-gb", type=float, default=32.0, help="serving: device memory budget")
     ap.add_argument("--sweep", default="1000,5000,20000", help="serving: extra arrival rates for the saturation sweep")
+    ap.add_argument("--no-composite", action="store_true", help="skip the composite-bank leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of 1 GiB (calibrates the HBM byte counters)")
     return ap.parse_args()
 
 
 COPY_PROBE_BYTES = 1 << 30
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.txt")
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_256x131072_fp32.txt")
 
 
 def copy_probe():
@@ -90,9 +91,9 @@ def measured_traffic(kernel: str, batch: int):
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("source_digest") != source_digest() or kv.get("kernel") != kernel or int(kv.get("batch", -1)) != batch:
+    if kv.get("source_digest") != source_digest() or int(kv.get("batch", -1)) != batch or kernel not in kv:
         return None
-    return float(kv["hbm_bytes_per_launch"])
+    return float(kv[kernel])
 
 
 def kernel_bytes(kind: str, plan, batch: int, b: int) -> float:
@@ -237,10 +238,50 @@ def main():
         "roofline": roofline,
     }
 
+    if not args.no_composite:
+        out["composite"] = composite_leg(args, x, B, W, ms_per_step)
     if not args.no_cpu:
         out.update(cpu_leg(args, plans, x_host, x, B, W))
     print(json.dumps(out), flush=True)
     return 0
+
+
+def composite_leg(args, x, B, W, ms_three_plans):
+    """The same Q set as one composite bank (one spectrum, one launch per
+    kernel, the frame summed over all 3 R rows): forward with row statistics,
+    per-segment best plane by energy, inverse from the whole bank."""
+    import torch
+    import paper_2603_29785_amd as qt
+    planes = [(q, "bisquare", 0.0) for q in W["qs"]]
+    p = qt.Plan(W["fs"], W["n"], 1.0, W["f_min"], W["f_max"], W["rows"], precision=args.precision, planes=planes)
+    ws = torch.empty(p.workspace_bytes(B), dtype=torch.uint8, device=x.device)
+    y = torch.empty((B, p.R, p.N_out), dtype=torch.complex128 if p.fp64 else torch.complex64, device=x.device)
+    m = torch.empty((B, p.R), dtype=y.dtype, device=x.device)
+    xr = torch.empty_like(x)
+    stream = torch.cuda.current_stream(x.device)
+
+    def step():
+        p.forward_metric(x, out=y, metric=m, ws=ws, stream=stream)
+        sel = p.select_planes(y, m, "energy", stream=stream)
+        p.inverse(y, out=xr, ws=ws, stream=stream)
+        return sel
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    reps = max(3, min(10, args.steps))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, best, _ = step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    counts = np.bincount(best.cpu().numpy(), minlength=p.planes).tolist()
+    del y, m, ws
+    return {"rows": p.R, "planes": p.planes, "ms_per_step": ms,
+            "samples_per_s": len(W["qs"]) * B * W["n"] / (ms * 1e-3),
+            "vs_separate_plans": ms_three_plans / ms, "best_plane_counts": counts,
+            "what": "forward with row statistics + energy selection + inverse of one %d-row bank "
+                    "(Q %s), samples counted once per plane" % (p.R, list(W["qs"]))}
 
 
 def cpu_leg(args, plans, x_host, x_dev, B, W):

@@ -211,6 +211,11 @@ qtam_status qtam_timing_collect(qtam_plan_t plan, const char** names, double* to
 
 const char* qtam_status_string(qtam_status status);
 
+/* Text of the last HIP runtime failure behind a QTAM_ERR_DEVICE or QTAM_ERR_OOM
+ * returned on the calling thread (call name, HIP error name and message);
+ * empty if none. Valid until the next call on this thread.                */
+const char* qtam_last_error(void);
+
 /* Library version string, e.g. "qtam-gfx950 1.0".                           */
 const char* qtam_version(void);
 

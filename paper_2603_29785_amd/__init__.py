@@ -4,7 +4,7 @@ gfx950 behind the C ABI of include/qtam.h.
 
 ``Plan`` builds a transform plan; ``Plan.forward`` / ``Plan.inverse`` run it on
 device tensors. Importing this package loads libqtam.so and fails if it has not
-been built (``paper_2603_29785_amd.build.build()``); there is no CPU fallback.
+been built (``python paper_2603_29785_amd/build.py``); there is no CPU fallback.
 """
 from .binding import (Plan, PlanInfo, QtamError, lib, status_string, version, EXPORTED,  # noqa: F401
                       FP32, FP64)

@@ -27,7 +27,11 @@ METRIC = {"energy": 0, "peak": 1}
 class QtamError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
-        super().__init__("%s: %s (status %d)" % (what, status_string(status), status))
+        detail = ""
+        if status in (QTAM_ERR_DEVICE, QTAM_ERR_OOM):
+            detail = lib.qtam_last_error().decode()
+        super().__init__("%s: %s (status %d)%s" % (what, status_string(status), status,
+                                                   ": " + detail if detail else ""))
 
 
 class c_params(ctypes.Structure):
@@ -87,13 +91,18 @@ class c_info(ctypes.Structure):
 EXPORTED = [
     "qtam_plan_create", "qtam_plan_info", "qtam_plan_destroy", "qtam_workspace_size",
     "qtam_forward", "qtam_inverse", "qtam_forward_adjoint", "qtam_inverse_adjoint",
-    "qtam_forward_metric", "qtam_select_planes", "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string", "qtam_version",
+    "qtam_forward_metric", "qtam_select_planes", "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string",
+    "qtam_last_error", "qtam_version",
 ]
 
 
 def _load():
+    # PyTorch's HIP runtime first: libqtam.so then binds to that same runtime
+    # (its soname is already loaded) instead of bringing a second copy into
+    # the process beside the one torch loads for its own tensors and streams.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libqtam.so not built at %s: run paper_2603_29785_amd.build.build()" % LIB_PATH)
+        raise ImportError("libqtam.so not built at %s: run python paper_2603_29785_amd/build.py" % LIB_PATH)
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
     L.qtam_plan_create.argtypes = [ctypes.POINTER(c_params), ctypes.POINTER(vp)]
@@ -120,6 +129,8 @@ def _load():
     L.qtam_timing_collect.restype = ctypes.c_int
     L.qtam_status_string.argtypes = [ctypes.c_int]
     L.qtam_status_string.restype = ctypes.c_char_p
+    L.qtam_last_error.argtypes = []
+    L.qtam_last_error.restype = ctypes.c_char_p
     L.qtam_version.argtypes = []
     L.qtam_version.restype = ctypes.c_char_p
     return L

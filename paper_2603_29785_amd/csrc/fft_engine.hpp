@@ -36,8 +36,14 @@ template <> struct Complex<double> { using type = double2; };
 template <typename C> __device__ __forceinline__ C c_add(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
 template <typename C> __device__ __forceinline__ C c_sub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
 template <typename C> __device__ __forceinline__ C c_conj(C a) { return C{a.x, -a.y}; }
+// Fused multiply-add with the product and the addend chosen here, not by the
+// compiler: every kernel instantiation then rounds the same way, so variants
+// of one kernel (with or without row statistics, say) write identical bits.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename C> __device__ __forceinline__ C c_mul(C a, C b) {
-  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+  return C{fmadd(a.x, b.x, -(a.y * b.y)), fmadd(a.x, b.y, a.y * b.x)};
 }
 template <typename C, typename T> __device__ __forceinline__ C c_scale(C a, T s) { return C{a.x * s, a.y * s}; }
 // a * (S i): S = +1 multiplies by i, S = -1 by -i
@@ -63,11 +69,13 @@ __device__ __forceinline__ C c_mul_root16(C a) {
   else if constexpr (k == 8) return C{-a.x, -a.y};
   else if constexpr (k == 12) return c_mul_si<-S>(a);
   else if constexpr (k == 2 || k == 6 || k == 10 || k == 14) {
-    // exp(S i pi/4 * k/2) = (cx + i S sy) / sqrt 2, cx, sy in {+1, -1}
+    // exp(S i pi/4 * k/2) = (cx + i sy) / sqrt 2, cx, sy in {+1, -1}
     constexpr T r = static_cast<T>(Root16::r2);
-    constexpr T cx = (k == 2 || k == 14) ? r : -r;
-    constexpr T sy = (k == 2 || k == 6) ? static_cast<T>(S) * r : -static_cast<T>(S) * r;
-    return C{a.x * cx - a.y * sy, a.x * sy + a.y * cx};
+    constexpr bool cpos = (k == 2 || k == 14);
+    constexpr bool spos = (k == 2 || k == 6) == (S > 0);
+    const T re = cpos ? (spos ? a.x - a.y : a.x + a.y) : (spos ? -a.x - a.y : a.y - a.x);
+    const T im = cpos ? (spos ? a.x + a.y : a.y - a.x) : (spos ? a.x - a.y : -a.x - a.y);
+    return C{re * r, im * r};
   } else {
     // k odd: cos / sin of 2 pi k/16 from the first-octant values
     constexpr int m = k % 8;                     // reduce by pi
@@ -76,7 +84,7 @@ __device__ __forceinline__ C c_mul_root16(C a) {
     constexpr T sn = static_cast<T>(m == 1 ? Root16::s1 : m == 3 ? Root16::c1 : m == 5 ? Root16::c1 : Root16::s1);
     constexpr T cx = sg * cs;
     constexpr T sy = sg * sn * static_cast<T>(S);
-    return C{a.x * cx - a.y * sy, a.x * sy + a.y * cx};
+    return C{fmadd(a.x, cx, -(a.y * sy)), fmadd(a.x, sy, a.y * cx)};
   }
 }
 
@@ -156,7 +164,8 @@ __device__ __forceinline__ void dft_small(C* a) {
 }
 
 // LDS index with one pad element every 32, which spreads power-of-two strides
-// over the banks.
+// over the banks; the map is affine inside each run of 32, so exchanges keep
+// constant instruction offsets.
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
 constexpr int lds_size(int l) { return l + l / 32 + 1; }
 

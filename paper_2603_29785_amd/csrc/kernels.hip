@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -215,11 +216,13 @@ __device__ __forceinline__ int xcd_major_block(int nblocks) {
 // Row statistics (sum and max of |Y|^2 over the row) of the E values each of
 // a row's TPR threads holds. Lanes of one row inside a wave combine by an xor
 // butterfly (every lane ends with the same bits); rows spanning several waves
-// then add the per-wave results in wave order through LDS. Every thread of the
-// block must call it.
+// then add the per-wave results in wave order through `part` (LDS the
+// transform no longer reads, NT/64 elements). Every thread of the block must
+// call it.
 template <typename T, int E, int TPR, int NT>
 __device__ __forceinline__ void row_stats(const typename Complex<T>::type (&v)[E], int tl, bool ok,
-                                          typename Complex<T>::type* __restrict__ dst) {
+                                          typename Complex<T>::type* __restrict__ dst,
+                                          typename Complex<T>::type* __restrict__ part) {
   using C = typename Complex<T>::type;
   constexpr int W = TPR < 64 ? TPR : 64;     // lanes of a row within one wave
   constexpr int WPR = TPR > 64 ? TPR / 64 : 1;
@@ -238,7 +241,6 @@ __device__ __forceinline__ void row_stats(const typename Complex<T>::type (&v)[E
   if constexpr (WPR == 1) {
     if (ok && tl == 0) *dst = C{e, m};
   } else {
-    __shared__ C part[NT / 64];
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = C{e, m};
     __syncthreads();
     if (ok && tl == 0) {
@@ -259,7 +261,7 @@ __device__ __forceinline__ void row_stats(const typename Complex<T>::type (&v)[E
 // slots outside it fall outside the resources and read 0, with no test.
 // Otherwise each slot is tested; ANALYTIC then computes the bisquare weight
 // scale_k (1 - (j/h_k)^2)^2 instead of reading the table.
-template <typename T, int L, bool ANALYTIC>
+template <typename T, int L, bool ANALYTIC, bool STATS>
 __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ Y,
     const RowMeta* __restrict__ rows, const typename Complex<T>::type* __restrict__ roww,
@@ -338,7 +340,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
   const uint32_t vb = static_cast<uint32_t>(g * L + tl) * sizeof(C);
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) bstore<C>(ry, v[i], vb, F::out_off(i) * sizeof(C));
-  if (stats != nullptr) row_stats<T, Geo::E, Geo::TPR, Geo::NT>(v, tl, ok, stats + gr);
+  if constexpr (STATS) row_stats<T, Geo::E, Geo::TPR, Geo::NT>(v, tl, ok, stats + gr, lds);
 }
 
 // Inverse rows: N_out-point FFT of each envelope row; the kept slots times the
@@ -486,39 +488,49 @@ __global__ __launch_bounds__((ColGeom<T, L1>::NT)) void k_inv_rows_rowst(
   }
 }
 
-// Overlap-add of the packed rows over each bin, in ascending row order (no
-// atomics), through the per-bin list of packed-entry indices, followed by the
-// pre-twist that turns the one-sided spectrum at bins p and N/2-p into the
+// Overlap-add. Each wave owns 64 consecutive bins p <= N/4 and their mirrors
+// q = N/2 - p. For each side it walks the rows whose kept support meets its
+// bins (a host list per wave, ascending row order, so every bin sums its
+// terms in ascending row order, with no atomics): lanes inside a row's support
+// add that row's packed entry, consecutive lanes reading consecutive entries;
+// lanes outside get an offset beyond the buffer and read 0. Then the
+// real-signal pre-twist turns the one-sided spectrum at p and N/2-p into the
 // half-size spectrum the synthesis FFT consumes.
+struct OlaRow {
+  int lo, span, base, pad;   // kept bins [lo, lo + span], packed entry of bin c at base + c
+};
+
 template <typename C>
-__device__ __forceinline__ C bin_sum(const C* __restrict__ Sseg, const int* __restrict__ ent, int a, int b) {
+__device__ __forceinline__ C ola_side(rsrc_t rs, const OlaRow* __restrict__ list, int a, int b, int c) {
   C acc{0, 0};
-  int i = a;
-  for (; i + 4 <= b; i += 4) {
-    const int e0 = ent[i], e1 = ent[i + 1], e2 = ent[i + 2], e3 = ent[i + 3];
-    const C s0 = Sseg[e0], s1 = Sseg[e1], s2 = Sseg[e2], s3 = Sseg[e3];
-    acc = c_add(acc, s0);
-    acc = c_add(acc, s1);
-    acc = c_add(acc, s2);
-    acc = c_add(acc, s3);
+#pragma unroll 4
+  for (int i = a; i < b; ++i) {
+    const OlaRow r = list[i];
+    const bool in = static_cast<unsigned>(c - r.lo) <= static_cast<unsigned>(r.span);
+    const unsigned vo = in ? static_cast<unsigned>(r.base + c) * static_cast<unsigned>(sizeof(C)) : 0xFFFFFFFFu;
+    acc = c_add(acc, bload<C>(rs, vo));
   }
-  for (; i < b; ++i) acc = c_add(acc, Sseg[ent[i]]);
   return acc;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_ola(
     const typename Complex<T>::type* __restrict__ Sbuf, typename Complex<T>::type* __restrict__ Zout,
-    const int* __restrict__ bin_start, const int* __restrict__ bin_ent, int64_t half, int64_t sum_len,
-    Twiddle2<typename Complex<T>::type> tw2) {
+    const int* __restrict__ wave_start, const OlaRow* __restrict__ wave_rows, int64_t half, int64_t sum_len,
+    int nwaves, Twiddle2<typename Complex<T>::type> tw2) {
   using C = typename Complex<T>::type;
-  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (p > half / 2) return;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * 4 + static_cast<int>(threadIdx.x >> 6));
+  if (wave >= nwaves) return;
   const int64_t seg = blockIdx.y;
-  const C* Sseg = Sbuf + seg * sum_len;
-  const int64_t q = half - p;
-  C A = bin_sum(Sseg, bin_ent, bin_start[p], bin_start[p + 1]);
-  C B = bin_sum(Sseg, bin_ent, bin_start[q], bin_start[q + 1]);
+  const int p = wave * 64 + static_cast<int>(threadIdx.x & 63);
+  const int q = static_cast<int>(half) - p;
+  const rsrc_t rs = make_rsrc(Sbuf + seg * sum_len, static_cast<uint32_t>(sum_len * sizeof(C)));
+  const int a0 = __builtin_amdgcn_readfirstlane(wave_start[2 * wave]);
+  const int a1 = __builtin_amdgcn_readfirstlane(wave_start[2 * wave + 1]);
+  const int a2 = __builtin_amdgcn_readfirstlane(wave_start[2 * wave + 2]);
+  C A = ola_side<C>(rs, wave_rows, a0, a1, p);
+  C B = ola_side<C>(rs, wave_rows, a1, a2, q);
+  if (p > half / 2) return;
   if (p == 0) {   // DC and Nyquist: real parts only (irfft convention)
     A.y = 0;
     B.y = 0;
@@ -638,6 +650,15 @@ int ilog2(int64_t v) {
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Text of the last HIP failure seen on this thread (qtam_last_error).
+thread_local std::string g_last_error;
+
+qtam_status hip_failed(hipError_t e, const char* what, qtam_status st = QTAM_ERR_DEVICE) {
+  g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  (void)hipGetLastError();
+  return st;
+}
+
 }  // namespace
 
 struct qtam_plan_s {
@@ -648,8 +669,9 @@ struct qtam_plan_s {
   // device table pointers (precision of the plan)
   RowMeta* d_rows = nullptr;
   void* d_roww = nullptr;       // per row (scale, 1/h) of the analytic forward weight
-  int* d_bin_start = nullptr;   // [N/2+2] start of each bin's list of packed entries
-  int* d_bin_ent = nullptr;     // [sum_len] packed-entry index, ascending row per bin
+  int* d_ola_start = nullptr;   // [2 * ola_waves + 1] start of each overlap-add wave side's row list
+  OlaRow* d_ola_rows = nullptr; // rows meeting each wave side's bins, ascending
+  int ola_waves = 0;            // waves of 64 bins covering p = 0 .. N/4
   void* d_tab[4] = {};
   void* d_tw_out = nullptr;     // N_out, base powers
   void* d_tw_out_full = nullptr;  // N_out, every power
@@ -744,20 +766,29 @@ qtam_status upload(qtam_plan_s* pl) {
   for (int k = 0; k < hp.rows; ++k)
     rm[k] = RowMeta{hp.centre[k], hp.lo[k], hp.hi[k], static_cast<int>(hp.offset[k])};
   const size_t o_rows = blob.add(rm.data(), rm.size() * sizeof(RowMeta));
-  // per-bin lists of the packed entries that cover the bin, rows ascending
-  std::vector<int> start(hp.n_bins + 2, 0), ent(hp.sum_len > 0 ? hp.sum_len : 1, 0);
-  for (int k = 0; k < hp.rows; ++k)
-    for (int64_t c = hp.lo[k]; c <= hp.hi[k]; ++c) ++start[c + 1];
-  for (int64_t b = 0; b < hp.n_bins; ++b) start[b + 1] += start[b];
-  start[hp.n_bins + 1] = start[hp.n_bins];
-  {
-    std::vector<int> fill(start.begin(), start.end() - 1);
-    for (int k = 0; k < hp.rows; ++k)
-      for (int64_t c = hp.lo[k]; c <= hp.hi[k]; ++c)
-        ent[fill[c]++] = static_cast<int>(hp.offset[k] + (c - hp.lo[k]));
+  // overlap-add: per wave of 64 bins p (p <= N/4) and its mirror side q = N/2 - p,
+  // the rows whose kept support meets those bins, ascending
+  const int64_t quarter = hp.half / 2;
+  const int nw = static_cast<int>(quarter / 64 + 1);
+  std::vector<std::vector<OlaRow>> side(2 * size_t(nw));
+  for (int k = 0; k < hp.rows; ++k) {
+    const OlaRow r{hp.lo[k], hp.hi[k] - hp.lo[k], static_cast<int>(hp.offset[k]) - hp.lo[k], 0};
+    const int64_t pa = std::max<int64_t>(0, hp.lo[k]), pb = std::min<int64_t>(quarter, hp.hi[k]);
+    for (int64_t w = pa / 64; pa <= pb && w <= pb / 64; ++w) side[2 * w].push_back(r);
+    const int64_t qa = std::max<int64_t>(0, hp.half - hp.hi[k]), qb = std::min<int64_t>(quarter, hp.half - hp.lo[k]);
+    for (int64_t w = qa / 64; qa <= qb && w <= qb / 64; ++w) side[2 * w + 1].push_back(r);
   }
-  const size_t o_bstart = blob.add(start.data(), start.size() * sizeof(int));
-  const size_t o_bent = blob.add(ent.data(), ent.size() * sizeof(int));
+  std::vector<int> ola_start(2 * size_t(nw) + 1, 0);
+  std::vector<OlaRow> ola_rows;
+  for (size_t i = 0; i < side.size(); ++i) {
+    ola_start[i] = static_cast<int>(ola_rows.size());
+    ola_rows.insert(ola_rows.end(), side[i].begin(), side[i].end());
+  }
+  ola_start[side.size()] = static_cast<int>(ola_rows.size());
+  if (ola_rows.empty()) ola_rows.push_back(OlaRow{0, -1, 0, 0});
+  pl->ola_waves = nw;
+  const size_t o_bstart = blob.add(ola_start.data(), ola_start.size() * sizeof(int));
+  const size_t o_bent = blob.add(ola_rows.data(), ola_rows.size() * sizeof(OlaRow));
   size_t o_tab[4];
   const std::vector<double>* src[4] = {&hp.fwd_tab, &hp.dual_tab, &hp.afwd_tab, &hp.ainv_tab};
   for (int i = 0; i < 4; ++i) {
@@ -811,20 +842,18 @@ qtam_status upload(qtam_plan_s* pl) {
   twiddles_strided(tw, ncoarse, nfine, hp.n);
   const size_t o_c = blob.add(tw.data(), tw.size() * sizeof(T));
 
-  if (hipMalloc(reinterpret_cast<void**>(&pl->dmem), blob.bytes.size()) != hipSuccess) {
-    (void)hipGetLastError();
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->dmem), blob.bytes.size());
+  if (e != hipSuccess) {
     pl->dmem = nullptr;
-    return QTAM_ERR_OOM;
+    return hip_failed(e, "hipMalloc of the plan tables", QTAM_ERR_OOM);
   }
-  if (hipMemcpy(pl->dmem, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipGetLastError();
-    return QTAM_ERR_DEVICE;
-  }
+  e = hipMemcpy(pl->dmem, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_failed(e, "hipMemcpy of the plan tables");
   char* d = pl->dmem;
   pl->d_rows = reinterpret_cast<RowMeta*>(d + o_rows);
   pl->d_roww = d + o_rw;
-  pl->d_bin_start = reinterpret_cast<int*>(d + o_bstart);
-  pl->d_bin_ent = reinterpret_cast<int*>(d + o_bent);
+  pl->d_ola_start = reinterpret_cast<int*>(d + o_bstart);
+  pl->d_ola_rows = reinterpret_cast<OlaRow*>(d + o_bent);
   for (int i = 0; i < 4; ++i) pl->d_tab[i] = d + o_tab[i];
   pl->d_tw_out = d + o_out;
   pl->d_tw_out_full = d + o_out_full;
@@ -959,7 +988,10 @@ bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* o
       using Geo = RowGeom<T, (1 << LG)>;                                                               \
       const int blocks = static_cast<int>((total_rows + Geo::G - 1) / Geo::G);                         \
       if (forward) {                                                                                   \
-        auto kern = analytic ? k_fwd_rows<T, (1 << LG), true> : k_fwd_rows<T, (1 << LG), false>;      \
+        auto kern = stats ? (analytic ? k_fwd_rows<T, (1 << LG), true, true>                          \
+                                      : k_fwd_rows<T, (1 << LG), false, true>)                         \
+                          : (analytic ? k_fwd_rows<T, (1 << LG), true, false>                          \
+                                      : k_fwd_rows<T, (1 << LG), false, false>);                       \
         hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(Geo::NT), 0, st, static_cast<const C*>(in), \
                            static_cast<C*>(out), rows, static_cast<const C*>(roww),                    \
                            static_cast<const T*>(tab), R, int(total_rows), int(half), int(sum_len),    \
@@ -1173,10 +1205,9 @@ bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t s
   if (!ok) return false;
   {
     Timed tm(pl, K_OLA, st);
-    const int64_t pairs = half / 2 + 1;
-    hipLaunchKernelGGL((k_ola<T>), dim3(unsigned((pairs + 255) / 256), unsigned(segs)), dim3(256), 0, st,
-                       static_cast<const C*>(pack), static_cast<C*>(spec), pl->d_bin_start, pl->d_bin_ent,
-                       half, hp.sum_len, tw2_of<T>(pl));
+    hipLaunchKernelGGL((k_ola<T>), dim3(unsigned((pl->ola_waves + 3) / 4), unsigned(segs)), dim3(256), 0, st,
+                       static_cast<const C*>(pack), static_cast<C*>(spec), pl->d_ola_start, pl->d_ola_rows,
+                       half, hp.sum_len, pl->ola_waves, tw2_of<T>(pl));
   }
   if (!pl->four_step) {
     Timed tm(pl, K_SYN, st);
@@ -1226,7 +1257,7 @@ qtam_status run_op(qtam_plan_t pl, Op op, const void* in, void* out, int64_t bat
       ok = f64 ? run_synthesis<double>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st)
                : run_synthesis<float>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st);
     if (!ok) return QTAM_ERR_UNSUPPORTED;
-    if (hipGetLastError() != hipSuccess) return QTAM_ERR_DEVICE;
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
   }
   return QTAM_OK;
 }
@@ -1270,6 +1301,8 @@ void choose_geometry(qtam_plan_s* pl) {
 // ===========================================================================
 extern "C" {
 
+const char* qtam_last_error(void) { return g_last_error.c_str(); }
+
 const char* qtam_version(void) { return "qtam-gfx950 1.0"; }
 
 const char* qtam_status_string(qtam_status s) {
@@ -1298,10 +1331,10 @@ qtam_status qtam_plan_create(const qtam_params* params, qtam_plan_t* out) {
   choose_geometry(pl);
   pl->seg_bytes = layout_for(pl, 1).total;
   if (!(params->flags & QTAM_PLAN_HOST_ONLY) && pl->gpu_supported) {
-    if (hipGetDevice(&pl->device_id) != hipSuccess) {
-      (void)hipGetLastError();
+    const hipError_t e = hipGetDevice(&pl->device_id);
+    if (e != hipSuccess) {
       delete pl;
-      return QTAM_ERR_DEVICE;
+      return hip_failed(e, "hipGetDevice");
     }
     if (hipDeviceGetAttribute(&pl->num_cus, hipDeviceAttributeMultiprocessorCount, pl->device_id) != hipSuccess ||
         pl->num_cus < 1) {
@@ -1413,7 +1446,7 @@ qtam_status qtam_select_planes(qtam_plan_t pl, const void* y, const void* metric
                        reinterpret_cast<const uint4*>(ys), best + b0,
                        reinterpret_cast<uint4*>(static_cast<char*>(y_best) + size_t(b0) * size_t(units) * 16), units,
                        hp.planes);
-    if (hipGetLastError() != hipSuccess) return QTAM_ERR_DEVICE;
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
   }
   return QTAM_OK;
 }

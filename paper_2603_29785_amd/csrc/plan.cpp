@@ -194,16 +194,12 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
     hp.n_out = p.n_out;
   }
 
-  // Frame operator, mask, covering rows per bin.
+  // Frame operator and mask.
   hp.P.assign(hp.n_bins, 0.0);
-  hp.bin_klo.assign(hp.n_bins, RT);
-  hp.bin_khi.assign(hp.n_bins, -1);
   for (int32_t k = 0; k < RT; ++k)
     for (int64_t c = hp.lo[k]; c <= hp.hi[k]; ++c) {
       const double w = hp.win[hp.offset[k] + (c - hp.lo[k])];
       hp.P[c] += w * w;
-      hp.bin_klo[c] = std::min(hp.bin_klo[c], k);
-      hp.bin_khi[c] = std::max(hp.bin_khi[c], k);
     }
   const double pmax = *std::max_element(hp.P.begin(), hp.P.end());
   const double floor_abs = p.p_floor_rel * pmax;

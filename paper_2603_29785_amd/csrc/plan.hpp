@@ -41,7 +41,6 @@ struct HostPlan {
   // per bin
   std::vector<double> P;          // frame operator diagonal
   std::vector<uint8_t> M;         // reconstruction mask
-  std::vector<int32_t> bin_klo, bin_khi;   // first / last row whose kept support holds the bin
 
   double frame_A = 0.0, frame_B = 0.0, masked_fraction = 0.0;
 };
