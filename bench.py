@@ -105,6 +105,7 @@ def kernel_bytes(kind: str, plan, batch: int, b: int) -> float:
         "inv_rows": R * no * c + sl * c,                 # read envelopes, write the kept slots
         "overlap_add": sl * c + (N // 2) * c,            # read kept slots, write the half spectrum
         "spectrum_fft": N * b + (N // 2) * c,            # read signal, write spectrum
+        "spectrum_twist": 2 * (N // 2) * c,              # read and write the half spectrum in place
         "spectrum_fft_pass1": N * b + (N // 2) * c,
         "spectrum_fft_pass2": 2 * (N // 2) * c,
         "synthesis_fft": (N // 2) * c + N * b,

@@ -172,8 +172,12 @@ constexpr int lds_size(int l) { return l + l / 32 + 1; }
 // Twiddle table layouts: TW_POW stores the base powers w^1, w^2, w^4, w^8 of
 // each pass and forms the others by products (little table traffic, for
 // kernels that stream their data); TW_FULL stores every w^r, r in [1, R)
-// (no products, for kernels whose vector ALU is the limit).
-enum TwiddleMode { TW_POW = 0, TW_FULL = 1 };
+// (no products, for kernels whose vector ALU is the limit); TW_MIXED stores
+// every power for passes of stride at most kFullStride (a table of a few KiB
+// that stays in the L1 cache) and base powers for the longer strides.
+enum TwiddleMode { TW_POW = 0, TW_FULL = 1, TW_MIXED = 2 };
+constexpr int kFullStride = 16;
+constexpr bool tw_full_pass(int mode, int ns) { return mode == TW_FULL || (mode == TW_MIXED && ns <= kFullStride); }
 
 // PREFETCH: request the twiddles of the next pass before the LDS exchange
 // (more registers live across the barrier) instead of after it.
@@ -190,15 +194,16 @@ struct BlockFft {
   }
   static constexpr int R0 = radix(1);
   static constexpr int RL = radix(last_ns());
-  // number of stored powers of a radix-R pass: w^(2^s) < R, or all w^r, r < R
-  static constexpr int slots(int r) {
-    return TW == TW_FULL ? r - 1 : (r >= 16 ? 4 : r >= 8 ? 3 : r >= 4 ? 2 : r >= 2 ? 1 : 0);
+  // number of stored powers of the radix-R pass of stride ns: w^(2^s) < R,
+  // or all w^r, r < R
+  static constexpr int slots(int r, int ns) {
+    return tw_full_pass(TW, ns) ? r - 1 : (r >= 16 ? 4 : r >= 8 ? 3 : r >= 4 ? 2 : r >= 2 ? 1 : 0);
   }
   // start of the twiddle block of the pass with stride ns
   static constexpr int tw_offset(int ns) {
     int off = 0, n = 1;
     while (n < ns) {
-      if (n > 1) off += slots(radix(n)) * n;
+      if (n > 1) off += slots(radix(n), n) * n;
       n *= radix(n);
     }
     return off;
@@ -220,14 +225,14 @@ struct BlockFft {
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
       const uint32_t k = static_cast<uint32_t>((tl + q * TPR) & (NS - 1));
-      if constexpr (TW == TW_FULL) {
+      if constexpr (tw_full_pass(TW, NS)) {
 #pragma unroll
         for (int r = 1; r < R; ++r)
           w[q * R + r] = bload<C>(tw, k * sizeof(C), (tw_offset(NS) + (r - 1) * NS) * sizeof(C));
       } else {
         C a[16];
 #pragma unroll
-        for (int sl = 0; sl < slots(R); ++sl)
+        for (int sl = 0; sl < slots(R, NS); ++sl)
           a[1 << sl] = bload<C>(tw, k * sizeof(C), (tw_offset(NS) + sl * NS) * sizeof(C));
         if constexpr (R > 2) a[3] = c_mul(a[2], a[1]);
         if constexpr (R > 4) {

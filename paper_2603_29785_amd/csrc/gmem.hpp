@@ -25,48 +25,60 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
                                            static_cast<int>(bytes), kRawBufferWord3);
 }
 
+// Cache policy of one access (the instruction's cache-policy bits): kCacheNT
+// marks a stream that is not read again soon, so it does not displace lines
+// that are (gfx940-family encoding: bit 1 = NT).
+constexpr int kCacheDefault = 0;
+constexpr int kCacheNT = 2;
+
 template <typename V> struct BufIO;
 
 template <> struct BufIO<float2> {
+  template <int AUX>
   __device__ static __forceinline__ float2 load(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
   }
+  template <int AUX>
   __device__ static __forceinline__ void store(rsrc_t r, float2 v, uint32_t voff, uint32_t soff) {
     using U = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, voff, soff, AUX);
   }
 };
 
 template <> struct BufIO<double2> {
+  template <int AUX>
   __device__ static __forceinline__ double2 load(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
   }
+  template <int AUX>
   __device__ static __forceinline__ void store(rsrc_t r, double2 v, uint32_t voff, uint32_t soff) {
     using U = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, voff, soff, AUX);
   }
 };
 
 template <> struct BufIO<float> {
+  template <int AUX>
   __device__ static __forceinline__ float load(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
   }
 };
 
 template <> struct BufIO<double> {
+  template <int AUX>
   __device__ static __forceinline__ double load(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
   }
 };
 
-template <typename V>
+template <typename V, int AUX = kCacheDefault>
 __device__ __forceinline__ V bload(rsrc_t r, uint32_t voff, uint32_t soff = 0) {
-  return BufIO<V>::load(r, voff, soff);
+  return BufIO<V>::template load<AUX>(r, voff, soff);
 }
 
-template <typename V>
+template <typename V, int AUX = kCacheDefault>
 __device__ __forceinline__ void bstore(rsrc_t r, V v, uint32_t voff, uint32_t soff = 0) {
-  BufIO<V>::store(r, v, voff, soff);
+  BufIO<V>::template store<AUX>(r, v, voff, soff);
 }
 
 }  // namespace qtam

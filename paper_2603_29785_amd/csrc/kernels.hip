@@ -213,6 +213,23 @@ __device__ __forceinline__ int xcd_major_block(int nblocks) {
 // their baseband slots (c - s_k) mod N_out (roll to baseband, crop, zero pad),
 // the N_out-point inverse FFT runs in registers and LDS, and the envelope row
 // is stored. One unit of G consecutive rows per workgroup.
+// Cache policy of the envelope stores: Y is written once and not read again
+// by the forward, so streaming it past the L2 keeps the spectrum and the plan
+// tables, which every row re-reads, resident there (measured: the forward
+// rows kernel of the batched workload drops from 0.70 to 0.50 ms). Loads of
+// Y by the inverse keep the default policy (streaming them measured no gain
+// and slowed the overlap-add that follows).
+constexpr int kYStore = kCacheNT;
+constexpr int kYLoad = kCacheDefault;
+// The packed kept slots are read once, by the overlap-add after the whole
+// inverse-rows launch: streamed as well (measured 1-3% on both kernels).
+constexpr int kSStore = kCacheNT;
+
+// Hides a value's derivation from the optimiser (an empty asm that keeps it
+// in a VGPR), so per-element offsets stay one add from a precomputed base
+// instead of being refolded into an add and a shift per resource.
+__device__ __forceinline__ void opaque(unsigned& v) { asm volatile("" : "+v"(v)); }
+
 // Row statistics (sum and max of |Y|^2 over the row) of the E values each of
 // a row's TPR threads holds. Lanes of one row inside a wave combine by an xor
 // butterfly (every lane ends with the same bits); rows spanning several waves
@@ -269,7 +286,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const typename Complex<T>::type* __restrict__ tw, int nblocks, typename Complex<T>::type* __restrict__ stats) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, +1, TW_POW>;
+  using F = BlockFft<T, L, Geo::E, +1, TW_MIXED>;
   constexpr bool kWaveRow = Geo::TPR >= 64;   // every lane of a wave is on the same row
   __shared__ C lds[Geo::G * lds_size(L)];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
@@ -286,12 +303,18 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const rsrc_t rz = make_rsrc(spec + int64_t(seg) * half + rm.lo, ok ? static_cast<uint32_t>(len * sizeof(C)) : 0u);
     const rsrc_t rt = make_rsrc(tab + rm.off, ok ? static_cast<uint32_t>(len * sizeof(T)) : 0u);
     const int db = rm.s - rm.lo + tl;   // kept-bin index d = c - lo of the slot with offset 0
+    // byte offsets of d in both resources, advanced by constants (negative d
+    // wraps beyond the resource and reads 0)
+    unsigned bx = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(C));
+    unsigned bw = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(T));
+    opaque(bx);
+    opaque(bw);
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
       const int off = F::in_off(i);
-      const unsigned d = static_cast<unsigned>(db + (off < L / 2 ? off : off - L));
-      const C x = bload<C>(rz, d * static_cast<unsigned>(sizeof(C)));
-      const T w = bload<T>(rt, d * static_cast<unsigned>(sizeof(T)));
+      const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
+      const C x = bload<C>(rz, bx + j * static_cast<unsigned>(sizeof(C)));
+      const T w = bload<T>(rt, bw + j * static_cast<unsigned>(sizeof(T)));
       v[i] = C{x.x * w, x.y * w};
     }
   } else {
@@ -339,7 +362,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
   const rsrc_t ry = make_rsrc(Y + r0 * L, static_cast<uint32_t>(nrow * L * sizeof(C)));
   const uint32_t vb = static_cast<uint32_t>(g * L + tl) * sizeof(C);
 #pragma unroll
-  for (int i = 0; i < Geo::E; ++i) bstore<C>(ry, v[i], vb, F::out_off(i) * sizeof(C));
+  for (int i = 0; i < Geo::E; ++i) bstore<C, kYStore>(ry, v[i], vb, F::out_off(i) * sizeof(C));
   if constexpr (STATS) row_stats<T, Geo::E, Geo::TPR, Geo::NT>(v, tl, ok, stats + gr, lds);
 }
 
@@ -354,7 +377,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
     const typename Complex<T>::type* __restrict__ tw) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, -1, TW_POW>;
+  using F = BlockFft<T, L, Geo::E, -1, TW_MIXED>;
   constexpr bool kWaveRow = Geo::TPR >= 64;
   __shared__ C lds[Geo::G * lds_size(L)];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
@@ -364,7 +387,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
   const uint32_t vb = static_cast<uint32_t>(g * L + tl) * sizeof(C);
   C v[Geo::E];
 #pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = bload<C>(ry, vb, F::in_off(i) * sizeof(C));
+  for (int i = 0; i < Geo::E; ++i) v[i] = bload<C, kYLoad>(ry, vb, F::in_off(i) * sizeof(C));
   F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
   int gr = static_cast<int>(r0) + g;
   if constexpr (kWaveRow) gr = __builtin_amdgcn_readfirstlane(gr);
@@ -376,12 +399,16 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
   if constexpr (kWaveRow) {
     const rsrc_t rs = make_rsrc(Sbuf + int64_t(seg) * sum_len + rm.off, static_cast<uint32_t>(len * sizeof(C)));
     const rsrc_t rt = make_rsrc(tab + rm.off, static_cast<uint32_t>(len * sizeof(T)));
+    unsigned bs = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(C));
+    unsigned bw = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(T));
+    opaque(bs);
+    opaque(bw);
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
       const int off = F::out_off(i);
-      const unsigned d = static_cast<unsigned>(db + (off < L / 2 ? off : off - L));
-      const T w = bload<T>(rt, d * static_cast<unsigned>(sizeof(T)));
-      bstore<C>(rs, C{v[i].x * w, v[i].y * w}, d * static_cast<unsigned>(sizeof(C)));
+      const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
+      const T w = bload<T>(rt, bw + j * static_cast<unsigned>(sizeof(T)));
+      bstore<C, kSStore>(rs, C{v[i].x * w, v[i].y * w}, bs + j * static_cast<unsigned>(sizeof(C)));
     }
   } else {
     const rsrc_t rs = make_rsrc(Sbuf, static_cast<uint32_t>(int64_t(segs) * sum_len * sizeof(C)));
@@ -393,7 +420,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
       const int d = db + (off < L / 2 ? off : off - L);
       if (static_cast<unsigned>(d) < static_cast<unsigned>(len)) {
         const T w = bload<T>(rt, (rm.off + d) * sizeof(T));
-        bstore<C>(rs, C{v[i].x * w, v[i].y * w}, (sb + d) * sizeof(C));
+        bstore<C, kSStore>(rs, C{v[i].x * w, v[i].y * w}, (sb + d) * sizeof(C));
       }
     }
   }
@@ -673,8 +700,7 @@ struct qtam_plan_s {
   OlaRow* d_ola_rows = nullptr; // rows meeting each wave side's bins, ascending
   int ola_waves = 0;            // waves of 64 bins covering p = 0 .. N/4
   void* d_tab[4] = {};
-  void* d_tw_out = nullptr;     // N_out, base powers
-  void* d_tw_out_full = nullptr;  // N_out, every power
+  void* d_tw_out = nullptr;     // N_out, TW_MIXED layout (the row kernels)
   void* d_tw_half = nullptr;    // N/2 (single pass) or nullptr
   void* d_tw_n1 = nullptr;      // N1 (four-step, second pass length)
   void* d_tw_n2 = nullptr;      // N2 (four-step, first pass length)
@@ -727,15 +753,16 @@ void twiddles_strided(std::vector<T>& out, int64_t count, int64_t step, int64_t 
 // Per-pass twiddle table of the block FFT of length L with e values per
 // thread, in the order the engine reads it (see BlockFft::tw_offset): for
 // each pass with stride ns > 1 and radix R, exp(-2 pi i r k / (ns R)),
-// k in [0, ns), for r = 1, 2, 4, 8 (< R) (TW_POW) or every r in [1, R)
-// (TW_FULL).
+// k in [0, ns), for r = 1, 2, 4, 8 (< R) or for every r in [1, R), as
+// tw_full_pass(mode, ns) says.
 template <typename T>
-void stockham_twiddles(std::vector<T>& out, int64_t L, int64_t e, bool full) {
+void stockham_twiddles(std::vector<T>& out, int64_t L, int64_t e, int mode) {
   out.clear();
   auto radix = [&](int64_t ns) { return (L / ns >= e) ? e : L / ns; };
   for (int64_t ns = 1; ns < L; ns *= radix(ns)) {
     const int64_t R = radix(ns);
     if (ns == 1) continue;
+    const bool full = tw_full_pass(mode, static_cast<int>(ns));
     for (int64_t r = 1; r < R; r = full ? r + 1 : 2 * r)
       for (int64_t k = 0; k < ns; ++k) {
         const double a = -2.0 * M_PI * static_cast<double>(r * k) / static_cast<double>(ns * R);
@@ -805,25 +832,23 @@ qtam_status upload(qtam_plan_s* pl) {
   const size_t o_rw = blob.add(rw.data(), rw.size() * sizeof(T));
   const bool f64 = sizeof(T) == 8;
   std::vector<T> tw;
-  stockham_twiddles(tw, hp.n_out, engine_e(hp.n_out, f64), false);
+  stockham_twiddles(tw, hp.n_out, engine_e(hp.n_out, f64), TW_MIXED);
   const size_t o_out = blob.add(tw.data(), tw.size() * sizeof(T));
-  stockham_twiddles(tw, hp.n_out, engine_e(hp.n_out, f64), true);
-  const size_t o_out_full = blob.add(tw.data(), tw.size() * sizeof(T));
   size_t o_half = 0, o_n1 = 0, o_n2 = 0;
   if (!pl->four_step) {
-    stockham_twiddles(tw, hp.half, engine_e(hp.half, f64), false);
+    stockham_twiddles(tw, hp.half, engine_e(hp.half, f64), TW_POW);
     o_half = blob.add(tw.data(), tw.size() * sizeof(T));
   } else {
-    stockham_twiddles(tw, pl->n1, engine_e(pl->n1, f64), false);
+    stockham_twiddles(tw, pl->n1, engine_e(pl->n1, f64), TW_POW);
     o_n1 = blob.add(tw.data(), tw.size() * sizeof(T));
-    stockham_twiddles(tw, pl->n2, engine_e(pl->n2, f64), false);
+    stockham_twiddles(tw, pl->n2, engine_e(pl->n2, f64), TW_POW);
     o_n2 = blob.add(tw.data(), tw.size() * sizeof(T));
   }
   size_t o_r1 = 0, o_r2 = 0, o_rf = 0, o_rc = 0;
   if (pl->big_rows) {
-    stockham_twiddles(tw, pl->r1, engine_e(pl->r1, f64), false);
+    stockham_twiddles(tw, pl->r1, engine_e(pl->r1, f64), TW_POW);
     o_r1 = blob.add(tw.data(), tw.size() * sizeof(T));
-    stockham_twiddles(tw, pl->r2, engine_e(pl->r2, f64), false);
+    stockham_twiddles(tw, pl->r2, engine_e(pl->r2, f64), TW_POW);
     o_r2 = blob.add(tw.data(), tw.size() * sizeof(T));
     const int nbr = ilog2(hp.n_out);
     pl->twr_bits = (nbr + 1) / 2;
@@ -856,7 +881,6 @@ qtam_status upload(qtam_plan_s* pl) {
   pl->d_ola_rows = reinterpret_cast<OlaRow*>(d + o_bent);
   for (int i = 0; i < 4; ++i) pl->d_tab[i] = d + o_tab[i];
   pl->d_tw_out = d + o_out;
-  pl->d_tw_out_full = d + o_out_full;
   pl->d_tw_half = pl->four_step ? nullptr : d + o_half;
   pl->d_tw_n1 = pl->four_step ? d + o_n1 : nullptr;
   pl->d_tw_n2 = pl->four_step ? d + o_n2 : nullptr;
