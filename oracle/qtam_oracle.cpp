@@ -11,7 +11,8 @@
 //   * the spectrum is the full N-point complex DFT of the real input, of which
 //     bins 0..N/2 are kept (no real-FFT packing tricks);
 //   * transforms use an iterative radix-2 Cooley-Tukey FFT for power-of-two
-//     lengths and a direct O(n^2) DFT otherwise (or when asked for);
+//     lengths, a recursive split by the smallest prime factor for other
+//     composite lengths, and a direct O(n^2) DFT for primes (or when asked);
 //   * every twiddle is cos/sin of its own angle, never a recurrence.
 //
 // Readings of points the paper leaves open are listed beside the step that
@@ -88,11 +89,52 @@ void fft_radix2(int64_t n, const cd* in, cd* out, int sign) {
 
 bool g_force_direct = false;
 
+void dft(int64_t n, const cd* in, cd* out, int sign);
+
+// Cooley-Tukey split of a composite length n = p * m, p its smallest prime
+// factor: the p decimated sequences x[q + p t] are transformed (length m)
+// and combined, X[k] = sum_q w^(q k) F_q[k mod m], w = e^(sign 2 pi i / n),
+// every w^(qk) again from its own angle with qk reduced mod n in integers.
+void fft_split(int64_t n, int64_t p, const cd* in, cd* out, int sign) {
+  const int64_t m = n / p;
+  std::vector<cd> sub(static_cast<size_t>(m)), f(static_cast<size_t>(n));
+  for (int64_t q = 0; q < p; ++q) {
+    for (int64_t t = 0; t < m; ++t) sub[static_cast<size_t>(t)] = in[q + p * t];
+    dft(m, sub.data(), f.data() + q * m, sign);
+  }
+  std::vector<cd> tmp(static_cast<size_t>(n));
+  for (int64_t k = 0; k < n; ++k) {
+    cd acc(0.0, 0.0);
+    for (int64_t q = 0; q < p; ++q) {
+      const int64_t e = (q * k) % n;
+      const double ang = sign * 2.0 * kPi * static_cast<double>(e) / static_cast<double>(n);
+      acc += f[static_cast<size_t>(q * m + k % m)] * cd(std::cos(ang), std::sin(ang));
+    }
+    tmp[static_cast<size_t>(k)] = acc;
+  }
+  std::copy(tmp.begin(), tmp.end(), out);
+}
+
+int64_t smallest_factor(int64_t n) {
+  for (int64_t p = 2; p * p <= n; ++p)
+    if (n % p == 0) return p;
+  return n;
+}
+
+// Power-of-two lengths: radix-2; other composite lengths: split by their
+// smallest prime factor; primes (or when forced): the direct sum.
 void dft(int64_t n, const cd* in, cd* out, int sign) {
-  if (!g_force_direct && is_pow2(n))
-    fft_radix2(n, in, out, sign);
-  else
+  if (g_force_direct || n <= 1) {
     dft_direct(n, in, out, sign);
+  } else if (is_pow2(n)) {
+    fft_radix2(n, in, out, sign);
+  } else {
+    const int64_t p = smallest_factor(n);
+    if (p == n)
+      dft_direct(n, in, out, sign);
+    else
+      fft_split(n, p, in, out, sign);
+  }
 }
 
 // ---------------------------------------------------------------------------

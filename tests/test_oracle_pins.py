@@ -30,7 +30,7 @@ def rel(a, b):
 # DFT / spectrum / synthesis against numpy (a textbook library), and the
 # radix-2 path against the direct O(n^2) sum.
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 12, 16, 64, 100, 256, 1024, 4096])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 12, 16, 64, 100, 256, 1024, 4096, 24576, 20480, 997])
 def test_dft_matches_numpy(n):
     rng = np.random.default_rng(n)
     x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
@@ -38,8 +38,10 @@ def test_dft_matches_numpy(n):
     assert rel(o.dft(x, +1), np.fft.ifft(x) * n) < 1e-13
 
 
-@pytest.mark.parametrize("n", [16, 128, 512])
-def test_radix2_matches_direct(n):
+@pytest.mark.parametrize("n", [16, 128, 512, 12, 96, 105, 1155, 3 * 1024, 2 * 997])
+def test_fast_paths_match_direct(n):
+    """Radix-2 (powers of two) and the smallest-prime-factor split (other
+    composite lengths) against the direct O(n^2) sum."""
     rng = np.random.default_rng(7 + n)
     x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     fast = o.dft(x, -1)
