@@ -199,6 +199,82 @@ __global__ __launch_bounds__(256) void k_twist(typename Complex<T>::type* __rest
   if (q != p) z[q] = C{xq.x * h, xq.y * h};
 }
 
+// Segment lengths with N/2 = r * M2, r in {3, 5}, M2 a power of two: the
+// half-size transform splits into r interleaved length-M2 transforms
+// (decimation by r) and one radix-r combination.
+//   forward:  Zp[n1][n2] = z[n1 + r n2];  F_n1 = DFT_M2(Zp[n1]);
+//             Z[k2 + M2 k1] = sum_n1 e^{-2 pi i n1 k1 / r} e^{-2 pi i n1 k2 / (N/2)} F_n1[k2]
+//   inverse:  A_n1[k2] = e^{+2 pi i n1 k2 / (N/2)} sum_k1 Z[k2 + M2 k1] e^{+2 pi i n1 k1 / r};
+//             z[n1 + r n2] = IDFT_M2(A_n1)[n2]
+// k_permute moves a segment between the natural order z[n] and the decimated
+// rows Zp[n1][n2] (TO_ROWS) or back; k_radix does the combination.
+template <typename T, bool TO_ROWS>
+__global__ __launch_bounds__(256) void k_permute(const typename Complex<T>::type* __restrict__ in,
+                                                 typename Complex<T>::type* __restrict__ out, int r, int64_t m2) {
+  const int64_t half = r * m2;
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;   // index in the decimated rows
+  if (i >= half) return;
+  const int64_t n1 = i / m2, n2 = i - n1 * m2;
+  const int64_t n = n1 + r * n2;
+  const int64_t base = int64_t(blockIdx.y) * half;
+  if constexpr (TO_ROWS) out[base + i] = in[base + n];
+  else out[base + n] = in[base + i];
+}
+
+// cos / sin of 2 pi k / R for R = 3, 5
+template <typename T, int R>
+__device__ __forceinline__ typename Complex<T>::type root_r(int k) {
+  using C = typename Complex<T>::type;
+  if constexpr (R == 3) {
+    constexpr T c1 = static_cast<T>(-0.5), s1 = static_cast<T>(0.86602540378443864676);
+    return k == 0 ? C{1, 0} : (k == 1 ? C{c1, s1} : C{c1, -s1});
+  } else {
+    constexpr T c1 = static_cast<T>(0.30901699437494742410), s1 = static_cast<T>(0.95105651629515357212);
+    constexpr T c2 = static_cast<T>(-0.80901699437494742410), s2 = static_cast<T>(0.58778525229247312917);
+    return k == 0 ? C{1, 0} : k == 1 ? C{c1, s1} : k == 2 ? C{c2, s2} : k == 3 ? C{c2, -s2} : C{c1, -s1};
+  }
+}
+
+template <typename T, int R, int S>
+__global__ __launch_bounds__(256) void k_radix(const typename Complex<T>::type* __restrict__ in,
+                                               typename Complex<T>::type* __restrict__ out, int64_t m2,
+                                               Twiddle2<typename Complex<T>::type> tw2) {
+  using C = typename Complex<T>::type;
+  const int64_t k2 = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (k2 >= m2) return;
+  const int64_t base = int64_t(blockIdx.y) * R * m2;
+  C a[R], b[R];
+  if constexpr (S < 0) {
+    // F_n1[k2] times e^{-2 pi i n1 k2 / (N/2)} = tw2(2 n1 k2), then the radix-R DFT over n1
+#pragma unroll
+    for (int n1 = 0; n1 < R; ++n1) {
+      const C f = in[base + n1 * m2 + k2];
+      a[n1] = n1 == 0 ? f : c_mul(f, tw2(2 * n1 * k2));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      C acc = a[0];
+#pragma unroll
+      for (int n1 = 1; n1 < R; ++n1) acc = c_add(acc, c_mul(a[n1], c_conj(root_r<T, R>((n1 * k1) % R))));
+      b[k1] = acc;
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) out[base + k2 + m2 * k1] = b[k1];
+  } else {
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) a[k1] = in[base + k2 + m2 * k1];
+#pragma unroll
+    for (int n1 = 0; n1 < R; ++n1) {
+      C acc = a[0];
+#pragma unroll
+      for (int k1 = 1; k1 < R; ++k1) acc = c_add(acc, c_mul(a[k1], root_r<T, R>((n1 * k1) % R)));
+      b[n1] = n1 == 0 ? acc : c_mul(acc, c_conj(tw2(2 * n1 * k2)));
+    }
+#pragma unroll
+    for (int n1 = 0; n1 < R; ++n1) out[base + n1 * m2 + k2] = b[n1];
+  }
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
 // XCD i mod 8) and roughly in index order. Renumbering them so that XCD x
 // takes the x-th eighth of the units makes the workgroups resident on one XCD
@@ -320,7 +396,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
   } else {
     const rsrc_t rz = make_rsrc(spec, static_cast<uint32_t>(spec_elems * sizeof(C)));
     const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
-    const unsigned mask = static_cast<unsigned>(half - 1);
+
     const unsigned zb = static_cast<unsigned>(seg) * static_cast<unsigned>(half);
     const int cb = rm.s + tl;
     // X[c] of the slots in the kept support; other slots get an offset beyond
@@ -330,7 +406,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
       const int off = F::in_off(i);
       const int c = cb + (off < L / 2 ? off : off - L);   // slot tl + off holds offset j = slot or slot - L
       const bool in = ok && c >= rm.lo && c <= rm.hi;
-      const unsigned vo = in ? (zb + (static_cast<unsigned>(c) & mask)) * static_cast<unsigned>(sizeof(C))
+      const unsigned vo = in ? (zb + static_cast<unsigned>(c == half ? 0 : c)) * static_cast<unsigned>(sizeof(C))
                              : 0xFFFFFFFFu;
       v[i] = bload<C>(rz, vo);
     }
@@ -388,29 +464,43 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
   C v[Geo::E];
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) v[i] = bload<C, kYLoad>(ry, vb, F::in_off(i) * sizeof(C));
-  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
-  int gr = static_cast<int>(r0) + g;
-  if constexpr (kWaveRow) gr = __builtin_amdgcn_readfirstlane(gr);
-  if (gr >= total) return;
-  const int seg = gr / R;
-  const RowMeta rm = rows[gr - seg * R];
-  const int len = rm.hi - rm.lo + 1;
-  const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
   if constexpr (kWaveRow) {
+    // the row's weights are requested before the transform, so their latency
+    // hides behind it; rows past the end get empty resources
+    const int gr = __builtin_amdgcn_readfirstlane(static_cast<int>(r0) + g);
+    const bool ok = gr < total;
+    const int seg = ok ? gr / R : 0;
+    const RowMeta rm = rows[ok ? gr - seg * R : 0];
+    const int len = ok ? rm.hi - rm.lo + 1 : 0;
+    const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
     const rsrc_t rs = make_rsrc(Sbuf + int64_t(seg) * sum_len + rm.off, static_cast<uint32_t>(len * sizeof(C)));
     const rsrc_t rt = make_rsrc(tab + rm.off, static_cast<uint32_t>(len * sizeof(T)));
     unsigned bs = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(C));
     unsigned bw = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(T));
     opaque(bs);
     opaque(bw);
+    T w[Geo::E];
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
       const int off = F::out_off(i);
       const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
-      const T w = bload<T>(rt, bw + j * static_cast<unsigned>(sizeof(T)));
-      bstore<C, kSStore>(rs, C{v[i].x * w, v[i].y * w}, bs + j * static_cast<unsigned>(sizeof(C)));
+      w[i] = bload<T>(rt, bw + j * static_cast<unsigned>(sizeof(T)));
+    }
+    F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) {
+      const int off = F::out_off(i);
+      const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
+      bstore<C, kSStore>(rs, C{v[i].x * w[i], v[i].y * w[i]}, bs + j * static_cast<unsigned>(sizeof(C)));
     }
   } else {
+    F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+    const int gr = static_cast<int>(r0) + g;
+    if (gr >= total) return;
+    const int seg = gr / R;
+    const RowMeta rm = rows[gr - seg * R];
+    const int len = rm.hi - rm.lo + 1;
+    const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
     const rsrc_t rs = make_rsrc(Sbuf, static_cast<uint32_t>(int64_t(segs) * sum_len * sizeof(C)));
     const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
     const unsigned sb = static_cast<unsigned>(seg) * static_cast<unsigned>(sum_len) + static_cast<unsigned>(rm.off);
@@ -657,12 +747,14 @@ using namespace qtam;
 namespace {
 
 enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_TWIST, K_FWD_ROWS, K_FWD_ROWS2, K_INV_ROWS, K_INV_ROWS2, K_OLA,
-            K_SYN, K_SYN1, K_SYN2, K_ROW_STATS, K_PLANE_BEST, K_GATHER, K_NUM };
+            K_SYN, K_SYN1, K_SYN2, K_ROW_STATS, K_PLANE_BEST, K_GATHER, K_SPEC_PERM, K_SPEC_RADIX, K_SYN_RADIX,
+            K_SYN_PERM, K_NUM };
 const char* const kKindName[K_NUM] = {"spectrum_fft", "spectrum_fft_pass1", "spectrum_fft_pass2",
                                        "spectrum_twist", "fwd_rows", "fwd_rows_pass2", "inv_rows",
                                        "inv_rows_pass2", "overlap_add", "synthesis_fft",
                                        "synthesis_fft_pass1", "synthesis_fft_pass2", "row_stats",
-                                       "plane_best", "gather_plane"};
+                                       "plane_best", "gather_plane", "spectrum_permute", "spectrum_radix",
+                                       "synthesis_radix", "synthesis_permute"};
 
 enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3 };
 
@@ -701,14 +793,16 @@ struct qtam_plan_s {
   int ola_waves = 0;            // waves of 64 bins covering p = 0 .. N/4
   void* d_tab[4] = {};
   void* d_tw_out = nullptr;     // N_out, TW_MIXED layout (the row kernels)
-  void* d_tw_half = nullptr;    // N/2 (single pass) or nullptr
+  void* d_tw_half = nullptr;    // M2 (single pass) or nullptr
   void* d_tw_n1 = nullptr;      // N1 (four-step, second pass length)
   void* d_tw_n2 = nullptr;      // N2 (four-step, first pass length)
   void* d_tw2_fine = nullptr;
   void* d_tw2_coarse = nullptr;
   int tw2_bits = 0;
-  bool four_step = false;
-  int64_t n1 = 0, n2 = 0;
+  bool four_step = false;       // the length-M2 transforms run as two passes
+  int64_t n1 = 0, n2 = 0;       // M2 = n1 * n2 when four_step
+  int radix_r = 1;              // N/2 = radix_r * m2
+  int64_t m2 = 0;               // power-of-two transform length of the spectrum
   bool big_rows = false;        // N_out beyond one workgroup: four-step rows through the workspace
   int64_t r1 = 0, r2 = 0;       // N_out = r1 * r2
   void* d_tw_r1 = nullptr;
@@ -836,7 +930,7 @@ qtam_status upload(qtam_plan_s* pl) {
   const size_t o_out = blob.add(tw.data(), tw.size() * sizeof(T));
   size_t o_half = 0, o_n1 = 0, o_n2 = 0;
   if (!pl->four_step) {
-    stockham_twiddles(tw, hp.half, engine_e(hp.half, f64), TW_POW);
+    stockham_twiddles(tw, pl->m2, engine_e(pl->m2, f64), TW_POW);
     o_half = blob.add(tw.data(), tw.size() * sizeof(T));
   } else {
     stockham_twiddles(tw, pl->n1, engine_e(pl->n1, f64), TW_POW);
@@ -861,7 +955,7 @@ qtam_status upload(qtam_plan_s* pl) {
   // two-level table of exp(-2 pi i m / N)
   const int nb = ilog2(hp.n);
   pl->tw2_bits = (nb + 1) / 2;
-  const int64_t nfine = int64_t(1) << pl->tw2_bits, ncoarse = hp.n >> pl->tw2_bits;
+  const int64_t nfine = int64_t(1) << pl->tw2_bits, ncoarse = (hp.n + nfine - 1) >> pl->tw2_bits;
   twiddles_strided(tw, nfine, 1, hp.n);
   const size_t o_f = blob.add(tw.data(), tw.size() * sizeof(T));
   twiddles_strided(tw, ncoarse, nfine, hp.n);
@@ -1086,7 +1180,7 @@ bool launch_inv_rows_rowst(int log2l1, const void* A, void* S, const RowMeta* ro
 // Workspace layout for a chunk of segments
 // ---------------------------------------------------------------------------
 struct WsLayout {
-  size_t spec = 0, tmp = 0, pack = 0, rows = 0, total = 0;
+  size_t spec = 0, tmp = 0, tmp2 = 0, pack = 0, rows = 0, total = 0;
 };
 
 WsLayout layout_for(const qtam_plan_s* pl, int64_t segs) {
@@ -1096,7 +1190,9 @@ WsLayout layout_for(const qtam_plan_s* pl, int64_t segs) {
   w.spec = off;
   off = align256(off + size_t(segs) * size_t(pl->hp.half) * cb);
   w.tmp = off;
-  if (pl->four_step) off = align256(off + size_t(segs) * size_t(pl->hp.half) * cb);
+  if (pl->four_step || pl->radix_r > 1) off = align256(off + size_t(segs) * size_t(pl->hp.half) * cb);
+  w.tmp2 = off;
+  if (pl->radix_r > 1) off = align256(off + size_t(segs) * size_t(pl->hp.half) * cb);
   w.pack = off;
   off = align256(off + size_t(segs) * size_t(pl->hp.sum_len) * cb);
   w.rows = off;
@@ -1115,6 +1211,7 @@ int64_t chunk_cap(const qtam_plan_s* pl) {
   const size_t lim = size_t(1) << 31;
   int64_t cap = per > lim ? 0 : int64_t(lim / per);
   if (pl->big_rows) cap = std::min<int64_t>(cap, 65535 / hp.rows);   // rows of a chunk index grid.y
+  cap = std::min<int64_t>(cap, 65535 / pl->radix_r);                  // decimated rows index grid.y
   return cap;
 }
 
@@ -1140,6 +1237,45 @@ Twiddle2<typename Complex<T>::type> tw2_of(const qtam_plan_s* pl) {
                      pl->tw2_bits};
 }
 
+// count length-M2 transforms (sign S) of consecutive M2-element blocks: one
+// LDS pass, or two passes through `tmp` (then `tmp` must differ from both).
+template <typename T, int S>
+bool transform_m2(qtam_plan_s* pl, const void* in, void* out, void* tmp, int64_t count, hipStream_t st, int k_one,
+                  int k_pass1, int k_pass2) {
+  const int64_t m2 = pl->m2;
+  if (!pl->four_step) {
+    Timed tm(pl, k_one, st);
+    return launch_fft_rows<T, S>(ilog2(m2), in, out, count, m2, pl->d_tw_half, st);
+  }
+  bool ok;
+  {
+    Timed tm(pl, k_pass1, st);
+    ok = launch_fft_cols<T, S>(ilog2(pl->n2), in, tmp, pl->n1, count, m2, pl->d_tw_n2, tw2_of<T>(pl), st,
+                               static_cast<int>(2 * pl->radix_r));
+  }
+  if (!ok) return false;
+  Timed tm(pl, k_pass2, st);
+  return launch_fft_rows_t<T, S>(ilog2(pl->n1), tmp, out, pl->n2, count, m2, pl->d_tw_n1, st);
+}
+
+// Radix-r combination of the decimated transforms (S = -1, analysis) or its
+// inverse (S = +1, synthesis), over segs segments.
+template <typename T, int S>
+bool launch_radix(qtam_plan_s* pl, const void* in, void* out, int64_t segs, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  Timed tm(pl, S < 0 ? K_SPEC_RADIX : K_SYN_RADIX, st);
+  const dim3 grid(unsigned((pl->m2 + 255) / 256), unsigned(segs));
+  if (pl->radix_r == 3)
+    hipLaunchKernelGGL((k_radix<T, 3, S>), grid, dim3(256), 0, st, static_cast<const C*>(in), static_cast<C*>(out),
+                       pl->m2, tw2_of<T>(pl));
+  else if (pl->radix_r == 5)
+    hipLaunchKernelGGL((k_radix<T, 5, S>), grid, dim3(256), 0, st, static_cast<const C*>(in), static_cast<C*>(out),
+                       pl->m2, tw2_of<T>(pl));
+  else
+    return false;
+  return true;
+}
+
 // analysis: real signal x -> rows (forward with T_FWD, inverse adjoint with T_AINV)
 template <typename T>
 bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t segs, char* ws,
@@ -1148,19 +1284,21 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
   const int64_t half = hp.half;
   void* spec = ws + lay.spec;
   bool ok;
-  if (!pl->four_step) {
-    Timed tm(pl, K_SPEC, st);
-    ok = launch_fft_rows<T, -1>(ilog2(half), x, spec, segs, half, pl->d_tw_half, st);
+  if (pl->radix_r == 1) {
+    ok = transform_m2<T, -1>(pl, x, spec, ws + lay.tmp, segs, st, K_SPEC, K_SPEC1, K_SPEC2);
   } else {
+    using C = typename Complex<T>::type;
     void* tmp = ws + lay.tmp;
+    void* tmp2 = ws + lay.tmp2;
     {
-      Timed tm(pl, K_SPEC1, st);
-      ok = launch_fft_cols<T, -1>(ilog2(pl->n2), x, tmp, pl->n1, segs, half, pl->d_tw_n2, tw2_of<T>(pl), st);
+      Timed tm(pl, K_SPEC_PERM, st);
+      hipLaunchKernelGGL((k_permute<T, true>), dim3(unsigned((half + 255) / 256), unsigned(segs)), dim3(256), 0, st,
+                         static_cast<const C*>(x), static_cast<C*>(tmp2), pl->radix_r, pl->m2);
     }
-    if (ok) {
-      Timed tm(pl, K_SPEC2, st);
-      ok = launch_fft_rows_t<T, -1>(ilog2(pl->n1), tmp, spec, pl->n2, segs, half, pl->d_tw_n1, st);
-    }
+    // single pass: tmp2 -> tmp; four-step: tmp2 -> tmp -> tmp2
+    void* f = pl->four_step ? tmp2 : tmp;
+    ok = transform_m2<T, -1>(pl, tmp2, f, tmp, segs * pl->radix_r, st, K_SPEC, K_SPEC1, K_SPEC2);
+    if (ok) ok = launch_radix<T, -1>(pl, f, spec, segs, st);
   }
   if (!ok) return false;
   {
@@ -1233,18 +1371,16 @@ bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t s
                        static_cast<const C*>(pack), static_cast<C*>(spec), pl->d_ola_start, pl->d_ola_rows,
                        half, hp.sum_len, pl->ola_waves, tw2_of<T>(pl));
   }
-  if (!pl->four_step) {
-    Timed tm(pl, K_SYN, st);
-    return launch_fft_rows<T, +1>(ilog2(half), spec, x, segs, half, pl->d_tw_half, st);
-  }
+  if (pl->radix_r == 1) return transform_m2<T, +1>(pl, spec, x, ws + lay.tmp, segs, st, K_SYN, K_SYN1, K_SYN2);
   void* tmp = ws + lay.tmp;
-  {
-    Timed tm(pl, K_SYN1, st);
-    ok = launch_fft_cols<T, +1>(ilog2(pl->n2), spec, tmp, pl->n1, segs, half, pl->d_tw_n2, tw2_of<T>(pl), st);
-  }
-  if (!ok) return false;
-  Timed tm(pl, K_SYN2, st);
-  return launch_fft_rows_t<T, +1>(ilog2(pl->n1), tmp, x, pl->n2, segs, half, pl->d_tw_n1, st);
+  void* tmp2 = ws + lay.tmp2;
+  if (!launch_radix<T, +1>(pl, spec, tmp2, segs, st)) return false;
+  void* f = pl->four_step ? tmp2 : tmp;
+  if (!transform_m2<T, +1>(pl, tmp2, f, tmp, segs * pl->radix_r, st, K_SYN, K_SYN1, K_SYN2)) return false;
+  Timed tm(pl, K_SYN_PERM, st);
+  hipLaunchKernelGGL((k_permute<T, false>), dim3(unsigned((half + 255) / 256), unsigned(segs)), dim3(256), 0, st,
+                     static_cast<const C*>(f), static_cast<C*>(x), pl->radix_r, pl->m2);
+  return true;
 }
 
 enum Op { OP_FORWARD, OP_INVERSE, OP_FWD_ADJ, OP_INV_ADJ };
@@ -1293,7 +1429,19 @@ void choose_geometry(qtam_plan_s* pl) {
   const int max_single = f64 ? kMaxLog2Single64 : kMaxLog2Single32;
   pl->gpu_supported = false;
   pl->unsupported_reason = QTAM_ERR_UNSUPPORTED;
-  if (!is_pow2(hp.n) || !is_pow2(hp.n_out)) return;
+  if (!is_pow2(hp.n_out)) return;
+  // N/2 = r * M2 with r in {1, 3, 5} and M2 a power of two
+  pl->radix_r = 0;
+  for (int r : {1, 3, 5})
+    if (hp.half % r == 0 && is_pow2(hp.half / r)) {
+      pl->radix_r = r;
+      break;
+    }
+  if (pl->radix_r == 0) {
+    pl->radix_r = 1;
+    return;
+  }
+  pl->m2 = hp.half / pl->radix_r;
   const int ln = ilog2(hp.n_out);
   if (ln < 2) return;
   pl->big_rows = ln > max_single;
@@ -1303,13 +1451,13 @@ void choose_geometry(qtam_plan_s* pl) {
     pl->r2 = int64_t(1) << l2;
     if (l1 > (f64 ? kMaxLog2Col64 : kMaxLog2Col32) || hp.rows > 65535) return;
   }
-  const int lh = ilog2(hp.half);
+  const int lh = ilog2(pl->m2);
   if (lh < 3) return;
   if (lh <= std::min(max_single, 13)) {
     pl->four_step = false;
   } else {
     pl->four_step = true;
-    const int l2 = lh / 2, l1 = lh - l2;   // N/2 = N1 * N2, N1 >= N2
+    const int l2 = lh / 2, l1 = lh - l2;   // M2 = N1 * N2, N1 >= N2
     pl->n1 = int64_t(1) << l1;
     pl->n2 = int64_t(1) << l2;
     if (l1 > (f64 ? kMaxLog2Col64 : kMaxLog2Col32) || l2 < 3) return;

@@ -92,7 +92,7 @@ def injected_segment(n: int, fs: float, rng: np.random.Generator, noise: str = "
         clean += c
         inj.append(Injection("chirp", dict(start=st, duration=d)))
     for _ in range(n_glitch):
-        f0 = float(rng.uniform(50.0, min(1500.0, 0.45 * fs)))
+        f0 = float(rng.uniform(min(50.0, 0.2 * fs), min(1500.0, 0.45 * fs)))   # low rates: below 0.45 fs
         q = float(rng.uniform(4.0, 20.0))
         t0 = float(rng.uniform(0.0, T))
         g = sine_gaussian(n, fs, f0, q, t0)

@@ -143,11 +143,26 @@ def test_calls_without_device_return_status():
     L.qtam_plan_destroy(None)
 
 
-def test_non_power_of_two_reports_unsupported_not_invalid():
-    gp = host_plan(sample_rate=4096.0, n_samples=24576, q=8.0, f_min=20.0, f_max=1000.0, n_rows=62)
+@pytest.mark.parametrize("n,odd_n_out", [(2 * 7 * 1024, False), (24576, True)])
+def test_unsupported_shapes_report_unsupported_not_invalid(n, odd_n_out):
+    """N/2 with an odd factor other than 3 or 5, or a non-power-of-two N_out
+    (here the longest window, the smallest valid one): valid plans the GPU
+    path does not run."""
+    kw = dict(sample_rate=4096.0, n_samples=n, q=8.0, f_min=20.0, f_max=1000.0, n_rows=62)
+    n_out = host_plan(**kw).info.max_len if odd_n_out else 0
+    gp = host_plan(n_out=n_out, **kw)
     dummy = ctypes.c_void_p(0x1000)
     st_ = binding.lib.qtam_forward(gp._h, dummy, dummy, 1, dummy, 1 << 30, None)
     assert st_ == binding.QTAM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n", [24576, 40960, 3 * 65536])
+def test_radix_three_and_five_lengths_are_supported(n):
+    gp = host_plan(sample_rate=4096.0, n_samples=n, q=8.0, f_min=20.0, f_max=1000.0, n_rows=62)
+    dummy = ctypes.c_void_p(0x1000)
+    # supported shape: a host-only plan fails on the missing device tables, not on the shape
+    st_ = binding.lib.qtam_forward(gp._h, dummy, dummy, 1, dummy, 1 << 30, None)
+    assert st_ == binding.QTAM_ERR_INVALID_ARG
 
 
 COMPOSITES = [

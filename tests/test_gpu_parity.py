@@ -67,6 +67,12 @@ CASES = [
     (4096.0, 32768, 8.0, 20.0, 2000.0, 128, 2),     # differentiable-workload plan, four-step spectrum
     (2048.0, 65536, 16.0, 10.0, 1024.0, 40, 2),     # N_out 8192 / 4096
     (4096.0, 131072, 4.0, 10.0, 2048.0, 256, 1),    # batched-workload plan, N_out 4096
+    # N/2 = r * 2^k: decimation by 3 or 5 around power-of-two transforms
+    (4096.0, 24576, 8.0, 20.0, 2000.0, 62, 3),      # 6 s at 4096 Hz (the paper's segment length), r = 3
+    (4096.0, 40960, 8.0, 16.0, 2048.0, 100, 2),     # 10 s, r = 5, band to Nyquist
+    (4096.0, 196608, 12.0, 10.0, 1500.0, 128, 1),   # 48 s, r = 3 around a four-step 32768-point transform
+    (96.0, 96, 2.0, 4.0, 48.0, 5, 4),               # tiny: N/2 = 48 = 3 * 16, band to Nyquist
+    (160.0, 160, 2.0, 4.0, 80.0, 8, 3),             # tiny: N/2 = 80 = 5 * 16
 ]
 
 
@@ -199,10 +205,10 @@ def test_errors_and_empty(torch_dev):
     with pytest.raises(qt.QtamError) as e:
         gp.forward(torch.zeros(2, 4096, device="cuda"), ws=tiny)
     assert e.value.status == 3
-    # non power-of-two segment length is not on the GPU path
-    bad = qt.Plan(4096.0, 24576, 8.0, 20.0, 1000.0, 62)
+    # N/2 with an odd factor other than 3 or 5 is not on the GPU path
+    bad = qt.Plan(4096.0, 14336, 8.0, 20.0, 1000.0, 62)
     with pytest.raises(qt.QtamError) as e:
-        bad.forward(torch.zeros(1, 24576, device="cuda"))
+        bad.forward(torch.zeros(1, 14336, device="cuda"))
     assert e.value.status == 2
 
 
