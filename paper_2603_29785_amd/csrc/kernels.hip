@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -516,6 +517,125 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
   }
 }
 
+// Envelope lengths M = N_out that are not powers of two (the paper's minimal
+// N_out, say): each row's length-M DFT by Bluestein's chirp-z identity,
+//   sum_u g[u] e^{S 2 pi i u m / M} = a[m] sum_u (g[u] a[u]) b[m - u],
+//   a[v] = e^{S pi i v^2 / M}, b[v] = conj(a[v]),
+// the convolution as a cyclic one of power-of-two length L >= 2M - 1: a
+// forward FFT, a product with Bhat = FFT_L(b wrapped) / L, an inverse FFT.
+// Tables (FP64-built): chirp a[0..M) and Bhat[0..L) of the transform's sign.
+template <typename T, int L, typename C, int E>
+__device__ __forceinline__ void chirp_convolve(C (&v)[E], C* lds, int tl, const C* __restrict__ bhat,
+                                               const C* __restrict__ tw) {
+  using Geo = RowGeom<T, L>;
+  static_assert(Geo::E == E, "row geometry");
+  using F = BlockFft<T, L, Geo::E, -1, TW_POW>;
+  using Fi = BlockFft<T, L, Geo::E, +1, TW_POW>;
+  F::run(v, lds, tl, F::twiddles(tw));
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) v[i] = c_mul(v[i], bhat[tl + F::out_off(i)]);
+  // back to the input order of the second transform
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) lds[lds_pad(tl + F::out_off(i))] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) v[i] = lds[lds_pad(tl + Fi::in_off(i))];
+  __syncthreads();
+  Fi::run(v, lds, tl, Fi::twiddles(tw));
+}
+
+// Forward rows, M not a power of two: gather the kept bins of each row at
+// their slots (c - s) mod M times the forward table and the chirp, then
+// Bluestein (sign +) and the output chirp; outputs m < M are stored.
+template <typename T, int L>
+__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows_bs(
+    const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ Y,
+    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int total, int half, int sum_len,
+    int64_t spec_elems, int M, const typename Complex<T>::type* __restrict__ chirp,
+    const typename Complex<T>::type* __restrict__ bhat, const typename Complex<T>::type* __restrict__ tw) {
+  using C = typename Complex<T>::type;
+  using Geo = RowGeom<T, L>;
+  using F = BlockFft<T, L, Geo::E, -1, TW_POW>;
+  using Fi = BlockFft<T, L, Geo::E, +1, TW_POW>;
+  __shared__ C lds[Geo::G * lds_size(L)];
+  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
+  const int gr = static_cast<int>(blockIdx.x) * Geo::G + g;
+  const bool ok = gr < total;
+  const int seg = ok ? gr / R : 0;
+  const RowMeta rm = rows[ok ? gr - seg * R : 0];
+  const rsrc_t rz = make_rsrc(spec, static_cast<uint32_t>(spec_elems * sizeof(C)));
+  const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
+  const unsigned zb = static_cast<unsigned>(seg) * static_cast<unsigned>(half);
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int u = tl + F::in_off(i);                 // Bluestein slot; < M holds data
+    const int j = u <= M / 2 ? u : u - M;            // offset from the centre bin
+    const int c = rm.s + j;
+    const bool in = ok && u < M && c >= rm.lo && c <= rm.hi;
+    const unsigned vo = in ? (zb + static_cast<unsigned>(c == half ? 0 : c)) * static_cast<unsigned>(sizeof(C))
+                           : 0xFFFFFFFFu;
+    C x = bload<C>(rz, vo);
+    if (c == 0) x.y = 0;
+    if (c == half) x = C{x.y, 0};
+    const T w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off - rm.lo + c : 0) * sizeof(T));
+    const C a = chirp[u < M ? u : 0];   // x is 0 outside the support
+    v[i] = c_mul(C{x.x * w, x.y * w}, a);
+  }
+  chirp_convolve<T, L>(v, lds + g * lds_size(L), tl, bhat, tw);
+  if (!ok) return;
+  C* yrow = Y + int64_t(gr) * M;
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int m = tl + Fi::out_off(i);
+    if (m < M) yrow[m] = c_mul(v[i], chirp[m]);
+  }
+}
+
+// Inverse rows, M not a power of two: Bluestein (sign -) over each envelope
+// row, then the kept slots times the table into the packed buffer.
+template <typename T, int L>
+__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows_bs(
+    const typename Complex<T>::type* __restrict__ Y, typename Complex<T>::type* __restrict__ Sbuf,
+    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int total, int sum_len, int M,
+    const typename Complex<T>::type* __restrict__ chirp, const typename Complex<T>::type* __restrict__ bhat,
+    const typename Complex<T>::type* __restrict__ tw) {
+  using C = typename Complex<T>::type;
+  using Geo = RowGeom<T, L>;
+  using F = BlockFft<T, L, Geo::E, -1, TW_POW>;
+  using Fi = BlockFft<T, L, Geo::E, +1, TW_POW>;
+  __shared__ C lds[Geo::G * lds_size(L)];
+  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
+  const int gr = static_cast<int>(blockIdx.x) * Geo::G + g;
+  const bool ok = gr < total;
+  const C* yrow = Y + int64_t(ok ? gr : 0) * M;
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int u = tl + F::in_off(i);
+    const bool in = ok && u < M;
+    const int uc = in ? u : 0;
+    const C z = c_mul(yrow[uc], c_conj(chirp[uc]));
+    v[i] = in ? z : C{0, 0};
+  }
+  chirp_convolve<T, L>(v, lds + g * lds_size(L), tl, bhat, tw);
+  if (!ok) return;
+  const int seg = gr / R;
+  const RowMeta rm = rows[gr - seg * R];
+  C* srow = Sbuf + int64_t(seg) * sum_len + rm.off;
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int u = tl + Fi::out_off(i);
+    if (u >= M) continue;
+    const int j = u <= M / 2 ? u : u - M;
+    const int c = rm.s + j;
+    if (c < rm.lo || c > rm.hi) continue;
+    const C z = c_mul(v[i], c_conj(chirp[u]));
+    const T w = tab[rm.off + c - rm.lo];
+    srow[c - rm.lo] = C{z.x * w, z.y * w};
+  }
+}
+
 // Rows longer than one workgroup's LDS transform (four-step over the
 // workspace, N_out = L1 * L2, slot u = n1 + L1 n2, output m = k2 + L2 k1).
 // Forward, first pass: for every row, column n1 gathers its L2 slots from the
@@ -801,6 +921,12 @@ struct qtam_plan_s {
   int tw2_bits = 0;
   bool four_step = false;       // the length-M2 transforms run as two passes
   int64_t n1 = 0, n2 = 0;       // M2 = n1 * n2 when four_step
+  bool bluestein = false;       // N_out not a power of two: chirp-z rows of length bs_len
+  int64_t bs_len = 0;
+  void* d_bs_chirp = nullptr;   // [N_out] e^{+pi i v^2 / N_out}
+  void* d_bs_bf = nullptr;      // [bs_len] FFT of the wrapped conjugate chirp / bs_len (forward rows)
+  void* d_bs_bi = nullptr;      // [bs_len] FFT of the wrapped chirp / bs_len (inverse rows)
+  void* d_bs_tw = nullptr;      // Stockham twiddles of bs_len
   int radix_r = 1;              // N/2 = radix_r * m2
   int64_t m2 = 0;               // power-of-two transform length of the spectrum
   bool big_rows = false;        // N_out beyond one workgroup: four-step rows through the workspace
@@ -832,6 +958,27 @@ namespace {
 // ---------------------------------------------------------------------------
 // Table construction for the device
 // ---------------------------------------------------------------------------
+// In-place forward DFT (e^{-2 pi i k n / L}) of a power-of-two length in
+// FP64 on the host: bit reversal, then butterflies with every twiddle from
+// its own angle.
+void host_fft(std::vector<std::complex<double>>& a) {
+  const int64_t n = static_cast<int64_t>(a.size());
+  for (int64_t i = 1, j = 0; i < n; ++i) {
+    int64_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (int64_t len = 2; len <= n; len <<= 1)
+    for (int64_t i = 0; i < n; i += len)
+      for (int64_t k = 0; k < len / 2; ++k) {
+        const std::complex<double> w = std::polar(1.0, -2.0 * M_PI * static_cast<double>(k) / static_cast<double>(len));
+        const std::complex<double> u = a[i + k], t = a[i + k + len / 2] * w;
+        a[i + k] = u + t;
+        a[i + k + len / 2] = u - t;
+      }
+}
+
 // exp(-2 pi i m / L) for m = first, first + step, ... (count values),
 // interleaved, evaluated in FP64 and rounded once to T.
 template <typename T>
@@ -926,7 +1073,8 @@ qtam_status upload(qtam_plan_s* pl) {
   const size_t o_rw = blob.add(rw.data(), rw.size() * sizeof(T));
   const bool f64 = sizeof(T) == 8;
   std::vector<T> tw;
-  stockham_twiddles(tw, hp.n_out, engine_e(hp.n_out, f64), TW_MIXED);
+  if (pl->bluestein) tw.assign(2, T(0));
+  else stockham_twiddles(tw, hp.n_out, engine_e(hp.n_out, f64), TW_MIXED);
   const size_t o_out = blob.add(tw.data(), tw.size() * sizeof(T));
   size_t o_half = 0, o_n1 = 0, o_n2 = 0;
   if (!pl->four_step) {
@@ -952,6 +1100,41 @@ qtam_status upload(qtam_plan_s* pl) {
     twiddles_strided(tw, ncs, nf, hp.n_out);
     o_rc = blob.add(tw.data(), tw.size() * sizeof(T));
   }
+  size_t o_bsc = 0, o_bsf = 0, o_bsi = 0, o_bstw = 0;
+  if (pl->bluestein) {
+    const int64_t M = hp.n_out, Lb = pl->bs_len;
+    std::vector<std::complex<double>> a(M), bf(Lb), bi(Lb);
+    for (int64_t v = 0; v < M; ++v) {
+      const int64_t e = (v * v) % (2 * M);   // exact v^2 mod 2M
+      a[v] = std::polar(1.0, M_PI * static_cast<double>(e) / static_cast<double>(M));
+    }
+    for (int64_t v = 0; v < M; ++v) {
+      bf[v] = std::conj(a[v]);
+      bi[v] = a[v];
+      if (v > 0) {
+        bf[Lb - v] = std::conj(a[v]);
+        bi[Lb - v] = a[v];
+      }
+    }
+    host_fft(bf);
+    host_fft(bi);
+    std::vector<T> ta(2 * M), tf(2 * Lb), ti(2 * Lb);
+    for (int64_t v = 0; v < M; ++v) {
+      ta[2 * v] = static_cast<T>(a[v].real());
+      ta[2 * v + 1] = static_cast<T>(a[v].imag());
+    }
+    for (int64_t k = 0; k < Lb; ++k) {
+      tf[2 * k] = static_cast<T>(bf[k].real() / static_cast<double>(Lb));
+      tf[2 * k + 1] = static_cast<T>(bf[k].imag() / static_cast<double>(Lb));
+      ti[2 * k] = static_cast<T>(bi[k].real() / static_cast<double>(Lb));
+      ti[2 * k + 1] = static_cast<T>(bi[k].imag() / static_cast<double>(Lb));
+    }
+    o_bsc = blob.add(ta.data(), ta.size() * sizeof(T));
+    o_bsf = blob.add(tf.data(), tf.size() * sizeof(T));
+    o_bsi = blob.add(ti.data(), ti.size() * sizeof(T));
+    stockham_twiddles(tw, Lb, engine_e(Lb, f64), TW_POW);
+    o_bstw = blob.add(tw.data(), tw.size() * sizeof(T));
+  }
   // two-level table of exp(-2 pi i m / N)
   const int nb = ilog2(hp.n);
   pl->tw2_bits = (nb + 1) / 2;
@@ -975,6 +1158,12 @@ qtam_status upload(qtam_plan_s* pl) {
   pl->d_ola_rows = reinterpret_cast<OlaRow*>(d + o_bent);
   for (int i = 0; i < 4; ++i) pl->d_tab[i] = d + o_tab[i];
   pl->d_tw_out = d + o_out;
+  if (pl->bluestein) {
+    pl->d_bs_chirp = d + o_bsc;
+    pl->d_bs_bf = d + o_bsf;
+    pl->d_bs_bi = d + o_bsi;
+    pl->d_bs_tw = d + o_bstw;
+  }
   pl->d_tw_half = pl->four_step ? nullptr : d + o_half;
   pl->d_tw_n1 = pl->four_step ? d + o_n1 : nullptr;
   pl->d_tw_n2 = pl->four_step ? d + o_n2 : nullptr;
@@ -1121,6 +1310,36 @@ bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* o
                            static_cast<const T*>(tab), R, int(total_rows), int(sum_len),               \
                            int(total_rows / R), static_cast<const C*>(tw));                           \
       }                                                                                                \
+      return true;                                                                                     \
+    }                                                                                                  \
+    return false;
+    QTAM_POW2_CASES(X)
+#undef X
+    default: return false;
+  }
+}
+
+template <typename T>
+bool launch_rows_bs(bool forward, int log2l, const void* in, void* out, const RowMeta* rows, const void* tab, int R,
+                    int64_t total_rows, int64_t half, int64_t sum_len, int M, const void* chirp, const void* bhat,
+                    const void* tw, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  switch (log2l) {
+#define X(LG)                                                                                          \
+  case LG:                                                                                             \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Single32 : kMaxLog2Single64)) {                    \
+      using Geo = RowGeom<T, (1 << LG)>;                                                               \
+      const int blocks = static_cast<int>((total_rows + Geo::G - 1) / Geo::G);                         \
+      if (forward)                                                                                     \
+        hipLaunchKernelGGL((k_fwd_rows_bs<T, (1 << LG)>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st,  \
+                           static_cast<const C*>(in), static_cast<C*>(out), rows, static_cast<const T*>(tab), \
+                           R, int(total_rows), int(half), int(sum_len), (total_rows / R) * half, M,    \
+                           static_cast<const C*>(chirp), static_cast<const C*>(bhat), static_cast<const C*>(tw)); \
+      else                                                                                             \
+        hipLaunchKernelGGL((k_inv_rows_bs<T, (1 << LG)>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st,  \
+                           static_cast<const C*>(in), static_cast<C*>(out), rows, static_cast<const T*>(tab), \
+                           R, int(total_rows), int(sum_len), M, static_cast<const C*>(chirp),          \
+                           static_cast<const C*>(bhat), static_cast<const C*>(tw));                    \
       return true;                                                                                     \
     }                                                                                                  \
     return false;
@@ -1330,6 +1549,21 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
     }
     return true;
   }
+  if (pl->bluestein) {
+    using C = typename Complex<T>::type;
+    {
+      Timed tm(pl, K_FWD_ROWS, st);
+      if (!launch_rows_bs<T>(true, ilog2(pl->bs_len), spec, y, pl->d_rows, pl->d_tab[table], hp.rows, segs * hp.rows,
+                             half, hp.sum_len, hp.n_out, pl->d_bs_chirp, pl->d_bs_bf, pl->d_bs_tw, st))
+        return false;
+    }
+    if (stats) {
+      Timed tm(pl, K_ROW_STATS, st);
+      hipLaunchKernelGGL((k_row_stats<T>), dim3(unsigned(segs * hp.rows)), dim3(256), 0, st, static_cast<const C*>(y),
+                         static_cast<C*>(stats), int64_t(hp.n_out));
+    }
+    return true;
+  }
   Timed tm(pl, K_FWD_ROWS, st);
   return launch_rows<T>(true, table == T_FWD && pl->analytic_fwd, ilog2(hp.n_out), spec, y, pl->d_rows,
                         pl->d_roww, pl->d_tab[table], hp.rows, segs * hp.rows, half, hp.sum_len,
@@ -1359,6 +1593,10 @@ bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t s
       ok = launch_inv_rows_rowst<T>(ilog2(pl->r1), A, pack, pl->d_rows, pl->d_tab[table], hp.rows,
                                     segs * hp.rows, hp.sum_len, hp.n_out, pl->r2, pl->d_tw_r1, st);
     }
+  } else if (pl->bluestein) {
+    Timed tm(pl, K_INV_ROWS, st);
+    ok = launch_rows_bs<T>(false, ilog2(pl->bs_len), y, pack, pl->d_rows, pl->d_tab[table], hp.rows, segs * hp.rows,
+                           half, hp.sum_len, hp.n_out, pl->d_bs_chirp, pl->d_bs_bi, pl->d_bs_tw, st);
   } else {
     Timed tm(pl, K_INV_ROWS, st);
     ok = launch_rows<T>(false, false, ilog2(hp.n_out), y, pack, pl->d_rows, nullptr, pl->d_tab[table],
@@ -1429,7 +1667,14 @@ void choose_geometry(qtam_plan_s* pl) {
   const int max_single = f64 ? kMaxLog2Single64 : kMaxLog2Single32;
   pl->gpu_supported = false;
   pl->unsupported_reason = QTAM_ERR_UNSUPPORTED;
-  if (!is_pow2(hp.n_out)) return;
+  // N_out not a power of two: chirp-z rows of the next power of two >= 2 N_out - 1
+  pl->bluestein = !is_pow2(hp.n_out);
+  if (pl->bluestein) {
+    int64_t lb = 1;
+    while (lb < 2 * int64_t(hp.n_out) - 1) lb *= 2;
+    pl->bs_len = lb;
+    if (ilog2(lb) > max_single || ilog2(lb) < 2) return;
+  }
   // N/2 = r * M2 with r in {1, 3, 5} and M2 a power of two
   pl->radix_r = 0;
   for (int r : {1, 3, 5})
@@ -1444,7 +1689,7 @@ void choose_geometry(qtam_plan_s* pl) {
   pl->m2 = hp.half / pl->radix_r;
   const int ln = ilog2(hp.n_out);
   if (ln < 2) return;
-  pl->big_rows = ln > max_single;
+  pl->big_rows = !pl->bluestein && ln > max_single;
   if (pl->big_rows) {
     const int l2 = ln / 2, l1 = ln - l2;   // N_out = r1 * r2, r1 >= r2
     pl->r1 = int64_t(1) << l1;

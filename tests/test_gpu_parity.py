@@ -134,6 +134,25 @@ def test_paper_cap_plan_parity(torch_dev):
     assert rel(xr, op.inverse(op.forward(x))) <= 1e-10
 
 
+def test_paper_minimal_output_size_parity(torch_dev):
+    """The paper's smallest envelope, N_out = ceil(T max_gap) + 1 under the
+    literal cap (App. A), on its 6 s x 4096 Hz segments with 62 rows: an odd
+    length, so chirp-z rows around a radix-3 spectrum."""
+    torch = torch_dev
+    import math
+    fs, n, R, fmin, fmax = 4096.0, 24576, 62, 20.0, 2000.0
+    f = fmin * (fmax / fmin) ** (np.arange(R) / (R - 1))
+    n_out = math.ceil(n / fs * np.max(np.diff(f))) + 1
+    gp, op = plans(fs, n, 8.0, fmin, fmax, R, "fp64", cap_mode="paper", n_out=n_out)
+    assert gp.N_out == n_out and n_out & (n_out - 1)
+    x = np.random.default_rng(6).standard_normal((2, n))
+    Y = gp.forward(to_dev(torch, x, "fp64")).cpu().numpy()
+    assert Y.shape == (2, R, n_out)
+    assert rel(Y, op.forward(x)) <= 1e-12
+    xr = gp.inverse(torch.from_numpy(Y).cuda()).cpu().numpy()
+    assert rel(xr, op.inverse(op.forward(x))) <= 1e-10
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_batched_workload_sampled(torch_dev, precision):
     """256 segments x 131072 samples at the benchmark's launch configuration;
@@ -210,6 +229,40 @@ def test_errors_and_empty(torch_dev):
     with pytest.raises(qt.QtamError) as e:
         bad.forward(torch.zeros(1, 14336, device="cuda"))
     assert e.value.status == 2
+
+
+# Envelope lengths that are not powers of two (chirp-z rows): the smallest
+# valid N_out (the longest window), as the paper's minimal output size.
+ODD_NOUT = [
+    # (fs, N, Q, f_min, f_max, R, batch, precision)
+    (4096.0, 24576, 8.0, 20.0, 2000.0, 62, 2, "fp32"),
+    (4096.0, 24576, 8.0, 20.0, 2000.0, 62, 2, "fp64"),
+    (4096.0, 16384, 8.0, 20.0, 1000.0, 64, 3, "fp32"),
+    (1024.0, 1024, 4.0, 8.0, 400.0, 12, 5, "fp64"),
+]
+
+
+@pytest.mark.parametrize("case", ODD_NOUT, ids=[f"N{c[1]}_R{c[5]}_{c[7]}" for c in ODD_NOUT])
+def test_odd_envelope_length_parity(torch_dev, case):
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    fs, n, q, fmin, fmax, R, B, precision = case
+    n_out = qt.Plan(fs, n, q, fmin, fmax, R, host_only=True).info.max_len
+    assert n_out & (n_out - 1)
+    gp, op = plans(fs, n, q, fmin, fmax, R, precision, n_out=n_out)
+    print(f"odd N_out: N={n} R={R} N_out={n_out} {precision}", flush=True)
+    x = np.stack([synthetic.injected_segment(n, fs, synthetic.rng_for(12, i))[0] for i in range(B)])
+    xh = host_input(x, precision)
+    Y_ref = op.forward(xh)
+    Y = gp.forward(to_dev(torch, xh, precision)).cpu().numpy()
+    assert rel_rows(Y, Y_ref).max() <= TOL[precision]
+    Yc = Y_ref.astype(np.complex64).astype(np.complex128) if precision == "fp32" else Y_ref
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    xr = gp.inverse(torch.from_numpy(np.ascontiguousarray(Yc)).to(dtype=dt, device="cuda")).cpu().numpy()
+    assert rel_rows(xr, op.inverse(Yc)).max() <= TOL[precision]
+    # round trip returns the projection onto the covered bins
+    xr2 = gp.inverse(gp.forward(to_dev(torch, xh, precision))).cpu().numpy()
+    assert rel_rows(xr2, op.project(xh)).max() <= TOL[precision]
 
 
 LONG_ROWS = [
