@@ -143,13 +143,14 @@ def test_calls_without_device_return_status():
     L.qtam_plan_destroy(None)
 
 
-@pytest.mark.parametrize("n,odd_n_out", [(2 * 7 * 1024, False), (24576, True)])
-def test_unsupported_shapes_report_unsupported_not_invalid(n, odd_n_out):
+@pytest.mark.parametrize("fs,n,odd_n_out", [(4096.0, 2 * 7 * 1024, False), (16384.0, 1 << 20, True)])
+def test_unsupported_shapes_report_unsupported_not_invalid(fs, n, odd_n_out):
     """N/2 with an odd factor other than 3 or 5, or a non-power-of-two N_out
-    (here the longest window, the smallest valid one): valid plans the GPU
-    path does not run."""
-    kw = dict(sample_rate=4096.0, n_samples=n, q=8.0, f_min=20.0, f_max=1000.0, n_rows=62)
+    (the longest window, the smallest valid one) whose chirp-z rows exceed
+    one workgroup: valid plans the GPU path does not run."""
+    kw = dict(sample_rate=fs, n_samples=n, q=8.0, f_min=20.0, f_max=min(4000.0, fs / 4), n_rows=62)
     n_out = host_plan(**kw).info.max_len if odd_n_out else 0
+    assert not odd_n_out or n_out > 8192
     gp = host_plan(n_out=n_out, **kw)
     dummy = ctypes.c_void_p(0x1000)
     st_ = binding.lib.qtam_forward(gp._h, dummy, dummy, 1, dummy, 1 << 30, None)
