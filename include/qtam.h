@@ -174,6 +174,18 @@ qtam_status qtam_forward_adjoint(qtam_plan_t plan, const void* gy, void* gx, int
 qtam_status qtam_inverse_adjoint(qtam_plan_t plan, const void* gx, void* gy, int64_t batch,
                                  void* ws, size_t ws_bytes, qtam_stream_t stream);
 
+/* Dense full-rate tiles (App. C): dense [batch, R, N] complex (device),
+ *   T_k[tau] = (1/N) sum_b X[b] W_k[b] e^{+2 pi i b tau / N},  tau = 0..N-1,
+ * from the envelopes y [batch, R, N_out] (each row re-modulated to its
+ * carrier and band-limited up-sampled to N samples; this is the dense row the
+ * forward transform decimates). Needs N a power of two (else
+ * QTAM_ERR_UNSUPPORTED) and the workspace qtam_dense_workspace_size gives
+ * (0 when the plan has no dense path); one segment's tiles must stay below
+ * 2 GiB. Smaller workspaces that hold one segment are used in chunks.       */
+size_t qtam_dense_workspace_size(qtam_plan_t plan, int64_t batch);
+qtam_status qtam_dense(qtam_plan_t plan, const void* y, void* dense, int64_t batch,
+                       void* ws, size_t ws_bytes, qtam_stream_t stream);
+
 /* Plane metrics (the per-plane quality metric of the multi-Q extension,
  * App. A): which statistic of a plane scores it.                           */
 typedef enum { QTAM_METRIC_ENERGY = 0,   /* sum over the plane's rows and m of |Y|^2 */

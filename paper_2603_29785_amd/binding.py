@@ -92,7 +92,7 @@ EXPORTED = [
     "qtam_plan_create", "qtam_plan_info", "qtam_plan_destroy", "qtam_workspace_size",
     "qtam_forward", "qtam_inverse", "qtam_forward_adjoint", "qtam_inverse_adjoint",
     "qtam_forward_metric", "qtam_select_planes", "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string",
-    "qtam_last_error", "qtam_version",
+    "qtam_dense", "qtam_dense_workspace_size", "qtam_last_error", "qtam_version",
 ]
 
 
@@ -117,6 +117,10 @@ def _load():
         f = getattr(L, name)
         f.argtypes = [vp, vp, vp, i64, vp, sz, vp]
         f.restype = ctypes.c_int
+    L.qtam_dense.argtypes = [vp, vp, vp, i64, vp, sz, vp]
+    L.qtam_dense.restype = ctypes.c_int
+    L.qtam_dense_workspace_size.argtypes = [vp, i64]
+    L.qtam_dense_workspace_size.restype = sz
     L.qtam_forward_metric.argtypes = [vp, vp, vp, vp, i64, vp, sz, vp]
     L.qtam_forward_metric.restype = ctypes.c_int
     L.qtam_select_planes.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, i64, vp]
@@ -367,6 +371,29 @@ class Plan:
                                        ctypes.c_void_p(stream.cuda_stream)), "qtam_forward_metric")
         return y, m
 
+    def dense(self, y, out=None, ws=None, stream=None):
+        """Dense full-rate tiles [..., R, N] complex from envelopes [..., R, N_out]
+        (each row re-modulated and up-sampled to N samples, App. C)."""
+        torch = self._torch()
+        y = self._check_rows(y)
+        lead = y.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        d = out if out is not None else torch.empty(tuple(lead) + (self.R, self.N), dtype=self._complex_dtype(),
+                                                    device=y.device)
+        if batch == 0:
+            return d
+        need = int(lib.qtam_dense_workspace_size(self._h, batch))
+        if need == 0:
+            raise QtamError(QTAM_ERR_UNSUPPORTED, "qtam_dense")
+        if ws is None:
+            ws = torch.empty(need, dtype=torch.uint8, device=y.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(y.device)
+        _check(lib.qtam_dense(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(d.data_ptr()), int(batch),
+                              ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size()),
+                              ctypes.c_void_p(stream.cuda_stream)), "qtam_dense")
+        return d
+
     def select_planes(self, y, metric, kind="energy", stream=None):
         """Optimal plane per segment: (score [..., planes], best [...] int32,
         y_best [..., rows_per_plane, N_out])."""
@@ -426,7 +453,7 @@ class Plan:
         _check(lib.qtam_timing_enable(self._h, 1 if on else 0), "qtam_timing_enable")
 
     def timing_collect(self) -> dict:
-        n = 16
+        n = 32
         names = (ctypes.c_char_p * n)()
         ms = (ctypes.c_double * n)()
         cnt = (ctypes.c_int64 * n)()

@@ -276,6 +276,23 @@ __global__ __launch_bounds__(256) void k_radix(const typename Complex<T>::type* 
   }
 }
 
+// Dense tiles: row k of segment s as an N-point spectrum holding its packed
+// kept entries at their bins lo..hi and zeros elsewhere (the inverse FFT of
+// that row is the dense tile). One thread per output bin, rows in grid.y.
+template <typename T>
+__global__ __launch_bounds__(256) void k_place(const typename Complex<T>::type* __restrict__ Sbuf,
+                                               typename Complex<T>::type* __restrict__ D, const RowMeta* __restrict__ rows,
+                                               int R, int64_t n, int64_t sum_len) {
+  using C = typename Complex<T>::type;
+  const int64_t b = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (b >= n) return;
+  const int64_t gr = blockIdx.y;
+  const int64_t seg = gr / R;
+  const RowMeta rm = rows[gr - seg * R];
+  const bool in = b >= rm.lo && b <= rm.hi;
+  D[gr * n + b] = in ? Sbuf[seg * sum_len + rm.off + (b - rm.lo)] : C{0, 0};
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
 // XCD i mod 8) and roughly in index order. Renumbering them so that XCD x
 // takes the x-th eighth of the units makes the workgroups resident on one XCD
@@ -868,15 +885,16 @@ namespace {
 
 enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_TWIST, K_FWD_ROWS, K_FWD_ROWS2, K_INV_ROWS, K_INV_ROWS2, K_OLA,
             K_SYN, K_SYN1, K_SYN2, K_ROW_STATS, K_PLANE_BEST, K_GATHER, K_SPEC_PERM, K_SPEC_RADIX, K_SYN_RADIX,
-            K_SYN_PERM, K_NUM };
+            K_SYN_PERM, K_DENSE_PLACE, K_DENSE_FFT, K_DENSE_FFT1, K_DENSE_FFT2, K_NUM };
 const char* const kKindName[K_NUM] = {"spectrum_fft", "spectrum_fft_pass1", "spectrum_fft_pass2",
                                        "spectrum_twist", "fwd_rows", "fwd_rows_pass2", "inv_rows",
                                        "inv_rows_pass2", "overlap_add", "synthesis_fft",
                                        "synthesis_fft_pass1", "synthesis_fft_pass2", "row_stats",
                                        "plane_best", "gather_plane", "spectrum_permute", "spectrum_radix",
-                                       "synthesis_radix", "synthesis_permute"};
+                                       "synthesis_radix", "synthesis_permute", "dense_place", "dense_fft",
+                                       "dense_fft_pass1", "dense_fft_pass2"};
 
-enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3 };
+enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3, T_DENSE = 4 };
 
 constexpr int kMaxLog2Single32 = 14;   // LDS-resident FFT up to 16384 points (FP32)
 constexpr int kMaxLog2Single64 = 13;   // and 8192 points (FP64)
@@ -911,7 +929,7 @@ struct qtam_plan_s {
   int* d_ola_start = nullptr;   // [2 * ola_waves + 1] start of each overlap-add wave side's row list
   OlaRow* d_ola_rows = nullptr; // rows meeting each wave side's bins, ascending
   int ola_waves = 0;            // waves of 64 bins covering p = 0 .. N/4
-  void* d_tab[4] = {};
+  void* d_tab[5] = {};
   void* d_tw_out = nullptr;     // N_out, TW_MIXED layout (the row kernels)
   void* d_tw_half = nullptr;    // M2 (single pass) or nullptr
   void* d_tw_n1 = nullptr;      // N1 (four-step, second pass length)
@@ -921,6 +939,12 @@ struct qtam_plan_s {
   int tw2_bits = 0;
   bool four_step = false;       // the length-M2 transforms run as two passes
   int64_t n1 = 0, n2 = 0;       // M2 = n1 * n2 when four_step
+  bool dense_ok = false;        // N a power of two: dense tiles available
+  bool dense_four_step = false; // N-point dense transforms in two passes, N = dn1 * dn2
+  int64_t dn1 = 0, dn2 = 0;
+  void* d_tw_dense = nullptr;   // Stockham twiddles of N (single pass)
+  void* d_tw_dn1 = nullptr;
+  void* d_tw_dn2 = nullptr;
   bool bluestein = false;       // N_out not a power of two: chirp-z rows of length bs_len
   int64_t bs_len = 0;
   void* d_bs_chirp = nullptr;   // [N_out] e^{+pi i v^2 / N_out}
@@ -1057,9 +1081,13 @@ qtam_status upload(qtam_plan_s* pl) {
   pl->ola_waves = nw;
   const size_t o_bstart = blob.add(ola_start.data(), ola_start.size() * sizeof(int));
   const size_t o_bent = blob.add(ola_rows.data(), ola_rows.size() * sizeof(OlaRow));
-  size_t o_tab[4];
-  const std::vector<double>* src[4] = {&hp.fwd_tab, &hp.dual_tab, &hp.afwd_tab, &hp.ainv_tab};
-  for (int i = 0; i < 4; ++i) {
+  size_t o_tab[5];
+  // dense tiles: Z = sqrt(N/N_out) DFT_{N_out}(Y) at the kept bins, and the
+  // 1/N of the N-point inverse DFT, one constant per entry
+  const std::vector<double> dense_tab(
+      hp.sum_len, std::sqrt(static_cast<double>(hp.n) / static_cast<double>(hp.n_out)) / static_cast<double>(hp.n));
+  const std::vector<double>* src[5] = {&hp.fwd_tab, &hp.dual_tab, &hp.afwd_tab, &hp.ainv_tab, &dense_tab};
+  for (int i = 0; i < 5; ++i) {
     std::vector<T> v(src[i]->begin(), src[i]->end());
     o_tab[i] = blob.add(v.data(), v.size() * sizeof(T));
   }
@@ -1135,6 +1163,18 @@ qtam_status upload(qtam_plan_s* pl) {
     stockham_twiddles(tw, Lb, engine_e(Lb, f64), TW_POW);
     o_bstw = blob.add(tw.data(), tw.size() * sizeof(T));
   }
+  size_t o_dt = 0, o_dn1 = 0, o_dn2 = 0;
+  if (pl->dense_ok) {
+    if (!pl->dense_four_step) {
+      stockham_twiddles(tw, hp.n, engine_e(hp.n, f64), TW_POW);
+      o_dt = blob.add(tw.data(), tw.size() * sizeof(T));
+    } else {
+      stockham_twiddles(tw, pl->dn1, engine_e(pl->dn1, f64), TW_POW);
+      o_dn1 = blob.add(tw.data(), tw.size() * sizeof(T));
+      stockham_twiddles(tw, pl->dn2, engine_e(pl->dn2, f64), TW_POW);
+      o_dn2 = blob.add(tw.data(), tw.size() * sizeof(T));
+    }
+  }
   // two-level table of exp(-2 pi i m / N)
   const int nb = ilog2(hp.n);
   pl->tw2_bits = (nb + 1) / 2;
@@ -1156,8 +1196,13 @@ qtam_status upload(qtam_plan_s* pl) {
   pl->d_roww = d + o_rw;
   pl->d_ola_start = reinterpret_cast<int*>(d + o_bstart);
   pl->d_ola_rows = reinterpret_cast<OlaRow*>(d + o_bent);
-  for (int i = 0; i < 4; ++i) pl->d_tab[i] = d + o_tab[i];
+  for (int i = 0; i < 5; ++i) pl->d_tab[i] = d + o_tab[i];
   pl->d_tw_out = d + o_out;
+  if (pl->dense_ok) {
+    pl->d_tw_dense = pl->dense_four_step ? nullptr : d + o_dt;
+    pl->d_tw_dn1 = pl->dense_four_step ? d + o_dn1 : nullptr;
+    pl->d_tw_dn2 = pl->dense_four_step ? d + o_dn2 : nullptr;
+  }
   if (pl->bluestein) {
     pl->d_bs_chirp = d + o_bsc;
     pl->d_bs_bf = d + o_bsf;
@@ -1572,12 +1617,11 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
 
 // synthesis: rows -> real signal (inverse with T_DUAL, forward adjoint with T_AFWD)
 template <typename T>
-bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t segs, char* ws,
-                   const WsLayout& lay, hipStream_t st) {
+bool inverse_rows(qtam_plan_s* pl, int table, const void* y, int64_t segs, char* ws, const WsLayout& lay,
+                  hipStream_t st) {
   using C = typename Complex<T>::type;
   const HostPlan& hp = pl->hp;
   const int64_t half = hp.half;
-  void* spec = ws + lay.spec;
   void* pack = ws + lay.pack;
   bool ok;
   if (pl->big_rows) {
@@ -1602,6 +1646,18 @@ bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t s
     ok = launch_rows<T>(false, false, ilog2(hp.n_out), y, pack, pl->d_rows, nullptr, pl->d_tab[table],
                         hp.rows, segs * hp.rows, half, hp.sum_len, pl->d_tw_out, st);
   }
+  return ok;
+}
+
+template <typename T>
+bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t segs, char* ws,
+                   const WsLayout& lay, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  const HostPlan& hp = pl->hp;
+  const int64_t half = hp.half;
+  void* spec = ws + lay.spec;
+  void* pack = ws + lay.pack;
+  bool ok = inverse_rows<T>(pl, table, y, segs, ws, lay, st);
   if (!ok) return false;
   {
     Timed tm(pl, K_OLA, st);
@@ -1619,6 +1675,51 @@ bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t s
   hipLaunchKernelGGL((k_permute<T, false>), dim3(unsigned((half + 255) / 256), unsigned(segs)), dim3(256), 0, st,
                      static_cast<const C*>(f), static_cast<C*>(x), pl->radix_r, pl->m2);
   return true;
+}
+
+// Dense tiles of a chunk: the kept DFT_{N_out} slots of every row (scaled),
+// placed at their bins of an N-point row, then N-point inverse transforms:
+// placed in `dtmp` and transformed into `dense` (one pass), or placed in
+// `dense`, first pass into `dtmp`, second pass back into `dense`.
+template <typename T>
+bool run_dense(qtam_plan_s* pl, const void* y, void* dense, int64_t segs, char* ws, const WsLayout& lay, void* dtmp,
+               hipStream_t st) {
+  using C = typename Complex<T>::type;
+  const HostPlan& hp = pl->hp;
+  if (!inverse_rows<T>(pl, T_DENSE, y, segs, ws, lay, st)) return false;
+  const int64_t count = segs * hp.rows;
+  {
+    Timed tm(pl, K_DENSE_PLACE, st);
+    hipLaunchKernelGGL((k_place<T>), dim3(unsigned((hp.n + 255) / 256), unsigned(count)), dim3(256), 0, st,
+                       static_cast<const C*>(static_cast<void*>(ws + lay.pack)),
+                       static_cast<C*>(pl->dense_four_step ? dense : dtmp), pl->d_rows, hp.rows, hp.n, hp.sum_len);
+  }
+  if (!pl->dense_four_step) {
+    Timed tm(pl, K_DENSE_FFT, st);
+    return launch_fft_rows<T, +1>(ilog2(hp.n), dtmp, dense, count, hp.n, pl->d_tw_dense, st);
+  }
+  bool ok;
+  {
+    Timed tm(pl, K_DENSE_FFT1, st);
+    ok = launch_fft_cols<T, +1>(ilog2(pl->dn2), dense, dtmp, pl->dn1, count, hp.n, pl->d_tw_dn2, tw2_of<T>(pl), st, 1);
+  }
+  if (!ok) return false;
+  Timed tm(pl, K_DENSE_FFT2, st);
+  return launch_fft_rows_t<T, +1>(ilog2(pl->dn1), dtmp, dense, pl->dn2, count, hp.n, pl->d_tw_dn1, st);
+}
+
+// Segments per dense chunk: rows index grid.y, each chunk's tiles below 2 GiB.
+int64_t dense_chunk_cap(const qtam_plan_s* pl) {
+  const HostPlan& hp = pl->hp;
+  const size_t per = size_t(hp.rows) * size_t(hp.n) * (hp.precision == QTAM_FP64 ? 16 : 8);
+  int64_t cap = std::min<int64_t>(chunk_cap(pl), 65535 / hp.rows);
+  cap = std::min<int64_t>(cap, per >= (size_t(1) << 31) ? 0 : int64_t(((size_t(1) << 31) - 1) / per));
+  return cap;
+}
+
+size_t dense_ws_bytes(const qtam_plan_s* pl, int64_t segs) {
+  const size_t cb = pl->hp.precision == QTAM_FP64 ? 16 : 8;
+  return align256(layout_for(pl, segs).total) + size_t(segs) * size_t(pl->hp.rows) * size_t(pl->hp.n) * cb;
 }
 
 enum Op { OP_FORWARD, OP_INVERSE, OP_FWD_ADJ, OP_INV_ADJ };
@@ -1709,6 +1810,21 @@ void choose_geometry(qtam_plan_s* pl) {
   }
   pl->gpu_supported = true;
   pl->unsupported_reason = QTAM_OK;
+  // dense tiles: N-point transforms, one pass or N = dn1 * dn2
+  pl->dense_ok = false;
+  if (is_pow2(hp.n)) {
+    const int lt = ilog2(hp.n);
+    if (lt <= max_single) {
+      pl->dense_four_step = false;
+      pl->dense_ok = true;
+    } else {
+      const int l2 = lt / 2, l1 = lt - l2;
+      pl->dense_four_step = true;
+      pl->dn1 = int64_t(1) << l1;
+      pl->dn2 = int64_t(1) << l2;
+      pl->dense_ok = l1 <= (f64 ? kMaxLog2Col64 : kMaxLog2Col32);
+    }
+  }
 }
 
 }  // namespace
@@ -1863,6 +1979,44 @@ qtam_status qtam_select_planes(qtam_plan_t pl, const void* y, const void* metric
                        reinterpret_cast<const uint4*>(ys), best + b0,
                        reinterpret_cast<uint4*>(static_cast<char*>(y_best) + size_t(b0) * size_t(units) * 16), units,
                        hp.planes);
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
+  }
+  return QTAM_OK;
+}
+
+size_t qtam_dense_workspace_size(qtam_plan_t pl, int64_t batch) {
+  if (!pl || batch < 1 || !pl->dense_ok) return 0;
+  const int64_t cap = dense_chunk_cap(pl);
+  if (cap < 1) return 0;
+  return dense_ws_bytes(pl, std::min(batch, cap));
+}
+
+qtam_status qtam_dense(qtam_plan_t pl, const void* y, void* dense, int64_t batch, void* ws, size_t ws_bytes,
+                       qtam_stream_t stream) {
+  if (!pl || batch < 0) return QTAM_ERR_INVALID_ARG;
+  if (batch == 0) return QTAM_OK;
+  if (!y || !dense || !ws) return QTAM_ERR_INVALID_ARG;
+  if (!pl->gpu_supported) return pl->unsupported_reason;
+  if (!pl->dense_ok || dense_chunk_cap(pl) < 1) return QTAM_ERR_UNSUPPORTED;
+  if (!pl->device) return QTAM_ERR_INVALID_ARG;
+  const HostPlan& hp = pl->hp;
+  const bool f64 = hp.precision == QTAM_FP64;
+  const size_t cb = f64 ? 16 : 8;
+  int64_t chunk = std::min(batch, dense_chunk_cap(pl));
+  while (chunk > 1 && dense_ws_bytes(pl, chunk) > ws_bytes) --chunk;
+  if (dense_ws_bytes(pl, chunk) > ws_bytes) return QTAM_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+    const int64_t segs = std::min(chunk, batch - b0);
+    const WsLayout lay = layout_for(pl, segs);
+    char* w = static_cast<char*>(ws);
+    void* dtmp = w + align256(lay.total);
+    const char* src = static_cast<const char*>(y) + size_t(b0) * size_t(hp.rows) * size_t(hp.n_out) * cb;
+    char* dst = static_cast<char*>(dense) + size_t(b0) * size_t(hp.rows) * size_t(hp.n) * cb;
+    const bool ok = f64 ? run_dense<double>(pl, src, dst, segs, w, lay, dtmp, st)
+                        : run_dense<float>(pl, src, dst, segs, w, lay, dtmp, st);
+    if (!ok) return QTAM_ERR_UNSUPPORTED;
     if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
   }
   return QTAM_OK;
