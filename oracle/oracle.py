@@ -53,7 +53,7 @@ def lib():
                                       ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_int32, dp,
-                                      ctypes.POINTER(ctypes.c_int32), dp]
+                                      ctypes.POINTER(ctypes.c_int32), dp, ctypes.c_double]
         L.ora_plan_destroy.argtypes = [ctypes.c_void_p]
         L.ora_plan_sizes.argtypes = [ctypes.c_void_p, i64p]
         L.ora_plan_rows.argtypes = [ctypes.c_void_p, dp, i64p, i64p, i64p, i64p]
@@ -64,6 +64,8 @@ def lib():
         for name in ("ora_spectrum", "ora_forward", "ora_inverse", "ora_synthesis"):
             getattr(L, name).argtypes = [ctypes.c_void_p, dp, ctypes.c_int64, dp]
         L.ora_dense.argtypes = [ctypes.c_void_p, dp, dp]
+        L.ora_tile_inverse.argtypes = [ctypes.c_void_p, dp, ctypes.c_int32, ctypes.c_int64, dp]
+        L.ora_tile_inverse.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -102,6 +104,7 @@ class OraclePlan:
     n_out: int = 0
     p_floor_rel: float = 1e-6
     planes: list | None = None     # [(q, window, param), ...]: composite bank, plane after plane
+    eps: float = 0.0               # stop-band value of every window (> 0: windows cover the whole band)
 
     def __post_init__(self):
         L = lib()
@@ -124,7 +127,7 @@ class OraclePlan:
                               float(self.f_max), int(self.rows), fr, int(self.window),
                               float(self.window_param), int(self.cap_mode), int(self.max_window),
                               int(self.norm_mode), int(self.n_out), float(self.p_floor_rel),
-                              int(npl), qs, ws, ps)
+                              int(npl), qs, ws, ps, float(self.eps))
         if not h:
             raise ValueError("oracle rejected the plan parameters")
         self._h = ctypes.c_void_p(h)
@@ -198,6 +201,16 @@ class OraclePlan:
         T = np.zeros((self.R, self.n), dtype=np.complex128)
         lib().ora_dense(self._h, _dp(x), _dp(T.view(np.float64)))
         return T
+
+    def tile_inverse(self, Y, k):
+        """The signal from row k alone by spectral division (regularised
+        windows): Y [batch, R, N_out] -> x [batch, N]."""
+        Y = np.ascontiguousarray(Y, dtype=np.complex128)
+        batch = Y.shape[0] if Y.ndim == 3 else 1
+        x = np.zeros((batch, self.n))
+        if lib().ora_tile_inverse(self._h, _dp(Y.view(np.float64)), int(k), batch, _dp(x)) != 0:
+            raise ValueError("tile inverse needs a window that is non-zero on its kept bins")
+        return x if Y.ndim == 3 else x[0]
 
     def project(self, x):
         """x_M = irfft(M * rfft(x)): what exact reconstruction returns."""

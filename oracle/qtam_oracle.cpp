@@ -232,9 +232,13 @@ struct PlaneSpec {
 
 // Returns 0 on success, 1 on invalid parameters. Rows are plane after plane,
 // each plane over the same frequency grid.
+// eps > 0: every window takes the value eps on the bins of the one-sided
+// band where its shape is zero (Sec. III regularised stop band; App. A),
+// before the normalisation, so that it is non-zero on all bins 0..N/2.
 int build_plan(Plan& pl, double fs, int64_t n, const std::vector<PlaneSpec>& planes, double fmin,
                double fmax, int32_t nrows, const double* freqs, int32_t cap_mode, int32_t max_window,
-               int32_t norm_mode, int32_t n_out, double tau) {
+               int32_t norm_mode, int32_t n_out, double tau, double eps) {
+  if (!(eps >= 0.0)) return 1;
   if (!(fs > 0.0) || n < 4 || (n % 2) != 0 || nrows < 1 || planes.empty()) return 1;
   for (const PlaneSpec& ps : planes)
     if (!(ps.q > 0.0)) return 1;
@@ -308,15 +312,21 @@ int build_plan(Plan& pl, double fs, int64_t n, const std::vector<PlaneSpec>& pla
     r.h = h;
     max_len = std::max(max_len, 2 * h + 1);
     // O5 window on the support |j| <= h, clipped to the one-sided band
-    // 0 <= s+j <= N/2 (no wrap into negative frequencies).
-    r.lo = std::max<int64_t>(0, r.s - h);
-    r.hi = std::min<int64_t>(half_bins, r.s + h);
+    // 0 <= s+j <= N/2 (no wrap into negative frequencies); with a stop-band
+    // value eps the kept bins are the whole band.
+    r.lo = eps > 0.0 ? 0 : std::max<int64_t>(0, r.s - h);
+    r.hi = eps > 0.0 ? half_bins : std::min<int64_t>(half_bins, r.s + h);
     if (r.lo > r.hi) return 1;
+    if (eps > 0.0) max_len = std::max(max_len, half_bins + 1);
     r.w.assign(static_cast<size_t>(r.hi - r.lo + 1), 0.0);
     double energy = 0.0;
     for (int64_t c = r.lo; c <= r.hi; ++c) {
+      // the stop band is every bin where the shape vanishes, the support's
+      // own end points included (the bisquare is zero there)
+      const bool inside = c >= r.s - h && c <= r.s + h;
       const double x = static_cast<double>(c - r.s) / static_cast<double>(h);
-      const double v = window_shape(window, x, window_param);
+      double v = inside ? window_shape(window, x, window_param) : 0.0;
+      if (eps > 0.0 && v == 0.0) v = eps;
       r.w[static_cast<size_t>(c - r.lo)] = v;
       energy += v * v;
     }
@@ -470,7 +480,8 @@ extern "C" {
 void* ora_plan_create(double fs, int64_t n, double q, double fmin, double fmax, int32_t nrows,
                       const double* freqs, int32_t window, double window_param, int32_t cap_mode,
                       int32_t max_window, int32_t norm_mode, int32_t n_out, double tau,
-                      int32_t n_planes, const double* qs, const int32_t* windows, const double* params) {
+                      int32_t n_planes, const double* qs, const int32_t* windows, const double* params,
+                      double eps) {
   std::vector<PlaneSpec> planes;
   if (n_planes > 0)
     for (int32_t p = 0; p < n_planes; ++p) planes.push_back(PlaneSpec{qs[p], windows[p], params[p]});
@@ -478,7 +489,7 @@ void* ora_plan_create(double fs, int64_t n, double q, double fmin, double fmax, 
     planes.push_back(PlaneSpec{q, window, window_param});
   Plan* pl = new Plan();
   if (build_plan(*pl, fs, n, planes, fmin, fmax, nrows, freqs, cap_mode, max_window, norm_mode, n_out,
-                 tau) != 0) {
+                 tau, eps) != 0) {
     delete pl;
     return nullptr;
   }
@@ -565,6 +576,33 @@ void ora_inverse(void* h, const double* Y, int64_t batch, double* x) {
 
 void ora_dense(void* h, const double* x, double* T) {
   dense_one(*static_cast<Plan*>(h), x, reinterpret_cast<cd*>(T));
+}
+
+// Recovery of the signal from the single tile k by spectral division
+// (Sec. III, regularised windows): the row's kept slots give
+// X[c] W_k[c] = sqrt(N/N_out) DFT_{N_out}(Y_k)[(c - s_k) mod N_out]; divide by
+// W_k[c] on every kept bin (zero elsewhere) and return to the time domain.
+// Y: [batch, R, N_out]; x: [batch, N]. Returns 1 if a kept W_k[c] is 0.
+int ora_tile_inverse(void* h, const double* Y, int32_t k, int64_t batch, double* x) {
+  const Plan& pl = *static_cast<Plan*>(h);
+  const int64_t R = static_cast<int64_t>(pl.rows.size()), M = pl.n_out;
+  if (k < 0 || k >= R) return 1;
+  const Row& r = pl.rows[static_cast<size_t>(k)];
+  const cd* Yc = reinterpret_cast<const cd*>(Y);
+  const double amp = std::sqrt(static_cast<double>(pl.n) / static_cast<double>(M));
+  std::vector<cd> F(static_cast<size_t>(M));
+  for (int64_t b = 0; b < batch; ++b) {
+    dft(M, Yc + (b * R + k) * M, F.data(), -1);
+    std::vector<cd> Xh(static_cast<size_t>(pl.nbins), cd(0.0, 0.0));
+    for (int64_t c = r.lo; c <= r.hi; ++c) {
+      const double w = r.w[static_cast<size_t>(c - r.lo)];
+      if (w == 0.0) return 1;
+      const int64_t u = ((c - r.s) % M + M) % M;
+      Xh[static_cast<size_t>(c)] = amp * F[static_cast<size_t>(u)] / w;
+    }
+    synthesis_real(pl, Xh, x + b * pl.n);
+  }
+  return 0;
 }
 
 // Real-signal synthesis from a one-sided spectrum (irfft convention).

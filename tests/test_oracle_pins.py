@@ -436,3 +436,48 @@ def test_selection_is_per_segment():
     assert list(best) == [1, 0]
     R = pc.rows_per_plane
     assert np.array_equal(Yb[0], Y[0, R:2 * R]) and np.array_equal(Yb[1], Y[1, :R])
+
+
+# --------------------------------------------------------------------------
+# Regularised stop band (Sec. III; App. A): windows non-zero on every bin,
+# so the signal comes back from any single tile by spectral division.
+# --------------------------------------------------------------------------
+def test_regularised_windows_and_single_tile_recovery():
+    kw = dict(fs=256.0, n=1024, q=4.0, f_min=10.0, f_max=100.0, rows=8)
+    eps = 1e-4
+    p = o.OraclePlan(eps=eps, **kw)
+    p0 = o.OraclePlan(**kw)
+    W, W0 = p.windows(), p0.windows()
+    assert np.all(W > 0) and p.N_out >= p.n // 2 + 1
+    # inside the support the shape is the plain window up to the normalisation;
+    # elsewhere (where the shape is zero) the value is eps times that factor
+    for k in range(p.R):
+        on = W0[k] > 0
+        ratio = W[k, on] / W0[k, on]
+        assert np.allclose(ratio, ratio[0], rtol=1e-13)
+        # the bisquare shape peaks at 1, so the plain window's peak is 1/||shape||
+        assert np.allclose(W[k, ~on], eps * ratio[0] * W0[k].max(), rtol=1e-12)
+    x = np.random.default_rng(41).standard_normal((2, p.n))
+    Y = p.forward(x)
+    for k in (0, 3, p.R - 1):
+        assert rel(p.tile_inverse(Y, k), x) < 1e-10
+    # the plain windows vanish at their support ends: no division possible
+    with pytest.raises(ValueError):
+        p0.tile_inverse(p0.forward(x), 2)
+
+
+def test_regularised_forward_matches_dense_definition():
+    """With eps the dense tile of the definition still equals the re-modulated
+    envelope (the full band is one kept support)."""
+    p = o.OraclePlan(fs=128.0, n=256, q=4.0, f_min=8.0, f_max=50.0, rows=5, eps=1e-3)
+    x = np.random.default_rng(42).standard_normal(p.n)
+    T = p.dense(x)
+    Y = p.forward(x)
+    t = p.row_table()
+    N, M = p.n, p.N_out
+    for k in range(p.R):
+        F = np.zeros(N, dtype=complex)
+        Yt = np.fft.fft(Y[k]) * np.sqrt(N / M)
+        for c in range(t["lo"][k], t["hi"][k] + 1):
+            F[c] = Yt[(c - t["centre"][k]) % M]
+        assert rel(np.fft.ifft(F), T[k]) < 1e-12
