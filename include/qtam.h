@@ -107,6 +107,11 @@ typedef struct {
   const double* plane_q;
   const int32_t* plane_window;
   const double* plane_window_param;
+  /* Regularised stop band (Sec. III; App. A): > 0 gives every window this
+   * value (before normalisation) on every bin of 0..N/2 where its shape is
+   * zero, so each row keeps the whole band (max L_k = N/2 + 1) and a single
+   * tile determines the signal (qtam_tile_inverse). 0: plain windows.      */
+  double window_eps;
 } qtam_params;
 
 typedef struct {
@@ -173,6 +178,15 @@ qtam_status qtam_forward_adjoint(qtam_plan_t plan, const void* gy, void* gx, int
  * gy [batch, R, N_out] complex.                                              */
 qtam_status qtam_inverse_adjoint(qtam_plan_t plan, const void* gx, void* gy, int64_t batch,
                                  void* ws, size_t ws_bytes, qtam_stream_t stream);
+
+/* The signal from the single row `row` of each segment by spectral division
+ * (Sec. III, regularised windows): X[c] = sqrt(N/N_out) DFT_{N_out}(Y_row)
+ * [(c - s_row) mod N_out] / W_row[c] on every bin, then the inverse real FFT.
+ * y [batch, R, N_out] -> x [batch, N]. Needs window_eps > 0
+ * (QTAM_ERR_INVALID_ARG otherwise) and a power-of-two N_out held by one
+ * workgroup (QTAM_ERR_UNSUPPORTED otherwise); workspace as qtam_inverse.    */
+qtam_status qtam_tile_inverse(qtam_plan_t plan, const void* y, int32_t row, void* x, int64_t batch,
+                              void* ws, size_t ws_bytes, qtam_stream_t stream);
 
 /* Dense full-rate tiles (App. C): dense [batch, R, N] complex (device),
  *   T_k[tau] = (1/N) sum_b X[b] W_k[b] e^{+2 pi i b tau / N},  tau = 0..N-1,

@@ -162,6 +162,7 @@ struct Plan {
   int64_t l_max = -1;       // cap on L_k (odd), -1 = no cap
   int64_t n_out = 0;
   double tau = 0.0;         // mask threshold relative to max P
+  double eps = 0.0;         // stop-band value (> 0: every row keeps the whole band)
   std::vector<Row> rows;
   std::vector<double> P;    // frame operator diagonal, per bin
   std::vector<unsigned char> M;  // reconstruction mask, per bin
@@ -239,6 +240,7 @@ int build_plan(Plan& pl, double fs, int64_t n, const std::vector<PlaneSpec>& pla
                double fmax, int32_t nrows, const double* freqs, int32_t cap_mode, int32_t max_window,
                int32_t norm_mode, int32_t n_out, double tau, double eps) {
   if (!(eps >= 0.0)) return 1;
+  pl.eps = eps;
   if (!(fs > 0.0) || n < 4 || (n % 2) != 0 || nrows < 1 || planes.empty()) return 1;
   for (const PlaneSpec& ps : planes)
     if (!(ps.q > 0.0)) return 1;
@@ -504,7 +506,8 @@ void ora_plan_sizes(void* h, int64_t* sizes) {
   const Plan& pl = *static_cast<Plan*>(h);
   int64_t mx = 0, sum = 0;
   for (const Row& r : pl.rows) {
-    mx = std::max(mx, 2 * r.h + 1);
+    // longest row: its window's support, or the whole band with a stop band
+    mx = std::max(mx, pl.eps > 0.0 ? pl.nbins : 2 * r.h + 1);
     sum += r.hi - r.lo + 1;
   }
   sizes[0] = static_cast<int64_t>(pl.rows.size());

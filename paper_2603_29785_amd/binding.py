@@ -56,6 +56,7 @@ class c_params(ctypes.Structure):
         ("plane_q", ctypes.POINTER(ctypes.c_double)),
         ("plane_window", ctypes.POINTER(ctypes.c_int32)),
         ("plane_window_param", ctypes.POINTER(ctypes.c_double)),
+        ("window_eps", ctypes.c_double),
     ]
 
 
@@ -92,7 +93,7 @@ EXPORTED = [
     "qtam_plan_create", "qtam_plan_info", "qtam_plan_destroy", "qtam_workspace_size",
     "qtam_forward", "qtam_inverse", "qtam_forward_adjoint", "qtam_inverse_adjoint",
     "qtam_forward_metric", "qtam_select_planes", "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string",
-    "qtam_dense", "qtam_dense_workspace_size", "qtam_last_error", "qtam_version",
+    "qtam_dense", "qtam_dense_workspace_size", "qtam_tile_inverse", "qtam_last_error", "qtam_version",
 ]
 
 
@@ -117,6 +118,8 @@ def _load():
         f = getattr(L, name)
         f.argtypes = [vp, vp, vp, i64, vp, sz, vp]
         f.restype = ctypes.c_int
+    L.qtam_tile_inverse.argtypes = [vp, vp, ctypes.c_int32, vp, i64, vp, sz, vp]
+    L.qtam_tile_inverse.restype = ctypes.c_int
     L.qtam_dense.argtypes = [vp, vp, vp, i64, vp, sz, vp]
     L.qtam_dense.restype = ctypes.c_int
     L.qtam_dense_workspace_size.argtypes = [vp, i64]
@@ -188,7 +191,7 @@ class Plan:
                  f_max: float = 0.0, n_rows: int = 0, freqs=None, window: str = "bisquare",
                  window_param: float = 0.0, cap_mode: str = "cover", max_window: int = 0,
                  norm_mode: str = "unit_energy", n_out: int = 0, p_floor_rel: float = 1e-6,
-                 precision: str = "fp32", host_only: bool = False, planes=None):
+                 precision: str = "fp32", host_only: bool = False, planes=None, window_eps: float = 0.0):
         """planes: optional list of (q, window, window_param) for a composite
         bank (rows plane after plane, one shared frame); q, window and
         window_param are then ignored."""
@@ -215,6 +218,7 @@ class Plan:
         p.p_floor_rel = float(p_floor_rel)
         p.precision = FP64 if precision in ("fp64", FP64, "float64") else FP32
         p.flags = PLAN_HOST_ONLY if host_only else 0
+        p.window_eps = float(window_eps)
         if planes:
             self._pq = np.array([float(t[0]) for t in planes], dtype=np.float64)
             self._pw = np.array([WINDOW[t[1]] if isinstance(t[1], str) else int(t[1]) for t in planes],
@@ -227,7 +231,7 @@ class Plan:
         self.params = dict(sample_rate=sample_rate, n_samples=n_samples, q=q, f_min=f_min, f_max=f_max,
                            n_rows=p.n_rows, window=window, window_param=window_param, cap_mode=cap_mode,
                            max_window=max_window, norm_mode=norm_mode, n_out=n_out,
-                           p_floor_rel=p_floor_rel, precision=precision, planes=planes)
+                           p_floor_rel=p_floor_rel, precision=precision, planes=planes, window_eps=window_eps)
         _check(lib.qtam_plan_create(ctypes.byref(p), ctypes.byref(self._h)), "qtam_plan_create")
         ci = c_info()
         _check(lib.qtam_plan_info(self._h, ctypes.byref(ci)), "qtam_plan_info")
@@ -370,6 +374,24 @@ class Plan:
                                        ctypes.c_size_t(ws.numel() * ws.element_size()),
                                        ctypes.c_void_p(stream.cuda_stream)), "qtam_forward_metric")
         return y, m
+
+    def tile_inverse(self, y, row, out=None, ws=None, stream=None):
+        """The signal [..., N] from row `row` alone of envelopes [..., R, N_out]
+        by spectral division (plans with window_eps > 0)."""
+        torch = self._torch()
+        y = self._check_rows(y)
+        lead = y.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        x = out if out is not None else torch.empty(tuple(lead) + (self.N,), dtype=self._real_dtype(),
+                                                    device=y.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(y.device)
+        ws = self._workspace(batch, y.device, ws)
+        _check(lib.qtam_tile_inverse(self._h, ctypes.c_void_p(y.data_ptr()), int(row), ctypes.c_void_p(x.data_ptr()),
+                                     int(batch), ctypes.c_void_p(ws.data_ptr()),
+                                     ctypes.c_size_t(ws.numel() * ws.element_size()),
+                                     ctypes.c_void_p(stream.cuda_stream)), "qtam_tile_inverse")
+        return x
 
     def dense(self, y, out=None, ws=None, stream=None):
         """Dense full-rate tiles [..., R, N] complex from envelopes [..., R, N_out]

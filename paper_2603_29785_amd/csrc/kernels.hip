@@ -293,6 +293,40 @@ __global__ __launch_bounds__(256) void k_place(const typename Complex<T>::type* 
   D[gr * n + b] = in ? Sbuf[seg * sum_len + rm.off + (b - rm.lo)] : C{0, 0};
 }
 
+// Single-tile recovery: row `row` of each segment, its N_out-point forward
+// transform, every slot whose bin c = s + j lies in 0..N/2 times the tile
+// table (sqrt(N/N_out) / W / N) into Sx[seg][c]. One segment per row group.
+template <typename T, int L>
+__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_tile_rows(
+    const typename Complex<T>::type* __restrict__ Y, typename Complex<T>::type* __restrict__ Sx,
+    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int row, int segs, int half,
+    const typename Complex<T>::type* __restrict__ tw) {
+  using C = typename Complex<T>::type;
+  using Geo = RowGeom<T, L>;
+  using F = BlockFft<T, L, Geo::E, -1, TW_MIXED>;
+  __shared__ C lds[Geo::G * lds_size(L)];
+  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
+  const int seg = static_cast<int>(blockIdx.x) * Geo::G + g;
+  const bool ok = seg < segs;
+  const rsrc_t ry = make_rsrc(Y + (int64_t(ok ? seg : 0) * R + row) * L, ok ? static_cast<uint32_t>(L * sizeof(C)) : 0u);
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) v[i] = bload<C>(ry, static_cast<uint32_t>(tl + F::in_off(i)) * sizeof(C));
+  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+  if (!ok) return;
+  const RowMeta rm = rows[row];
+  C* dst = Sx + int64_t(seg) * (half + 1);
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int off = F::out_off(i);
+    const int c = rm.s + tl + (off < L / 2 ? off : off - L);
+    if (c >= rm.lo && c <= rm.hi) {
+      const T w = tab[rm.off + c - rm.lo];
+      dst[c] = C{v[i].x * w, v[i].y * w};
+    }
+  }
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
 // XCD i mod 8) and roughly in index order. Renumbering them so that XCD x
 // takes the x-th eighth of the units makes the workgroups resident on one XCD
@@ -894,7 +928,7 @@ const char* const kKindName[K_NUM] = {"spectrum_fft", "spectrum_fft_pass1", "spe
                                        "synthesis_radix", "synthesis_permute", "dense_place", "dense_fft",
                                        "dense_fft_pass1", "dense_fft_pass2"};
 
-enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3, T_DENSE = 4 };
+enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3, T_DENSE = 4, T_TILE = 5 };
 
 constexpr int kMaxLog2Single32 = 14;   // LDS-resident FFT up to 16384 points (FP32)
 constexpr int kMaxLog2Single64 = 13;   // and 8192 points (FP64)
@@ -929,7 +963,9 @@ struct qtam_plan_s {
   int* d_ola_start = nullptr;   // [2 * ola_waves + 1] start of each overlap-add wave side's row list
   OlaRow* d_ola_rows = nullptr; // rows meeting each wave side's bins, ascending
   int ola_waves = 0;            // waves of 64 bins covering p = 0 .. N/4
-  void* d_tab[5] = {};
+  int* d_one_start = nullptr;   // overlap-add lists of a single row over all bins
+  OlaRow* d_one_rows = nullptr;
+  void* d_tab[6] = {};
   void* d_tw_out = nullptr;     // N_out, TW_MIXED layout (the row kernels)
   void* d_tw_half = nullptr;    // M2 (single pass) or nullptr
   void* d_tw_n1 = nullptr;      // N1 (four-step, second pass length)
@@ -1081,13 +1117,20 @@ qtam_status upload(qtam_plan_s* pl) {
   pl->ola_waves = nw;
   const size_t o_bstart = blob.add(ola_start.data(), ola_start.size() * sizeof(int));
   const size_t o_bent = blob.add(ola_rows.data(), ola_rows.size() * sizeof(OlaRow));
-  size_t o_tab[5];
+  // the same lists for one row holding every bin in order (single-tile recovery)
+  std::vector<int> one_start(2 * size_t(nw) + 1);
+  for (size_t i = 0; i < one_start.size(); ++i) one_start[i] = static_cast<int>(i);
+  const std::vector<OlaRow> one_rows(2 * size_t(nw), OlaRow{0, static_cast<int>(hp.half), 0, 0});
+  const size_t o_one_start = blob.add(one_start.data(), one_start.size() * sizeof(int));
+  const size_t o_one_rows = blob.add(one_rows.data(), one_rows.size() * sizeof(OlaRow));
+  size_t o_tab[6];
   // dense tiles: Z = sqrt(N/N_out) DFT_{N_out}(Y) at the kept bins, and the
   // 1/N of the N-point inverse DFT, one constant per entry
   const std::vector<double> dense_tab(
       hp.sum_len, std::sqrt(static_cast<double>(hp.n) / static_cast<double>(hp.n_out)) / static_cast<double>(hp.n));
-  const std::vector<double>* src[5] = {&hp.fwd_tab, &hp.dual_tab, &hp.afwd_tab, &hp.ainv_tab, &dense_tab};
-  for (int i = 0; i < 5; ++i) {
+  const std::vector<double>* src[6] = {&hp.fwd_tab, &hp.dual_tab, &hp.afwd_tab, &hp.ainv_tab, &dense_tab,
+                                       &hp.tile_tab};
+  for (int i = 0; i < 6; ++i) {
     std::vector<T> v(src[i]->begin(), src[i]->end());
     o_tab[i] = blob.add(v.data(), v.size() * sizeof(T));
   }
@@ -1196,7 +1239,9 @@ qtam_status upload(qtam_plan_s* pl) {
   pl->d_roww = d + o_rw;
   pl->d_ola_start = reinterpret_cast<int*>(d + o_bstart);
   pl->d_ola_rows = reinterpret_cast<OlaRow*>(d + o_bent);
-  for (int i = 0; i < 5; ++i) pl->d_tab[i] = d + o_tab[i];
+  pl->d_one_start = reinterpret_cast<int*>(d + o_one_start);
+  pl->d_one_rows = reinterpret_cast<OlaRow*>(d + o_one_rows);
+  for (int i = 0; i < 6; ++i) pl->d_tab[i] = d + o_tab[i];
   pl->d_tw_out = d + o_out;
   if (pl->dense_ok) {
     pl->d_tw_dense = pl->dense_four_step ? nullptr : d + o_dt;
@@ -1650,6 +1695,10 @@ bool inverse_rows(qtam_plan_s* pl, int table, const void* y, int64_t segs, char*
 }
 
 template <typename T>
+bool synthesize(qtam_plan_s* pl, const void* pack, int64_t slen, const int* starts, const OlaRow* list, void* x,
+                int64_t segs, char* ws, const WsLayout& lay, hipStream_t st);
+
+template <typename T>
 bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t segs, char* ws,
                    const WsLayout& lay, hipStream_t st) {
   using C = typename Complex<T>::type;
@@ -1659,11 +1708,23 @@ bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t s
   void* pack = ws + lay.pack;
   bool ok = inverse_rows<T>(pl, table, y, segs, ws, lay, st);
   if (!ok) return false;
+  return synthesize<T>(pl, pack, hp.sum_len, pl->d_ola_start, pl->d_ola_rows, x, segs, ws, lay, st);
+}
+
+// Overlap-add of packed entries (per-wave row lists `starts`, `list`; `slen`
+// entries per segment) with the real-signal pre-twist, then the inverse
+// half-size transform to the real signal x.
+template <typename T>
+bool synthesize(qtam_plan_s* pl, const void* pack, int64_t slen, const int* starts, const OlaRow* list, void* x,
+                int64_t segs, char* ws, const WsLayout& lay, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  const int64_t half = pl->hp.half;
+  void* spec = ws + lay.spec;
   {
     Timed tm(pl, K_OLA, st);
     hipLaunchKernelGGL((k_ola<T>), dim3(unsigned((pl->ola_waves + 3) / 4), unsigned(segs)), dim3(256), 0, st,
-                       static_cast<const C*>(pack), static_cast<C*>(spec), pl->d_ola_start, pl->d_ola_rows,
-                       half, hp.sum_len, pl->ola_waves, tw2_of<T>(pl));
+                       static_cast<const C*>(pack), static_cast<C*>(spec), starts, list, half, slen, pl->ola_waves,
+                       tw2_of<T>(pl));
   }
   if (pl->radix_r == 1) return transform_m2<T, +1>(pl, spec, x, ws + lay.tmp, segs, st, K_SYN, K_SYN1, K_SYN2);
   void* tmp = ws + lay.tmp;
@@ -1720,6 +1781,29 @@ int64_t dense_chunk_cap(const qtam_plan_s* pl) {
 size_t dense_ws_bytes(const qtam_plan_s* pl, int64_t segs) {
   const size_t cb = pl->hp.precision == QTAM_FP64 ? 16 : 8;
   return align256(layout_for(pl, segs).total) + size_t(segs) * size_t(pl->hp.rows) * size_t(pl->hp.n) * cb;
+}
+
+template <typename T>
+bool launch_tile_rows(qtam_plan_s* pl, const void* y, void* sx, int row, int64_t segs, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  const HostPlan& hp = pl->hp;
+  Timed tm(pl, K_INV_ROWS, st);
+  switch (ilog2(hp.n_out)) {
+#define X(LG)                                                                                          \
+  case LG:                                                                                             \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Single32 : kMaxLog2Single64)) {                    \
+      using Geo = RowGeom<T, (1 << LG)>;                                                               \
+      hipLaunchKernelGGL((k_tile_rows<T, (1 << LG)>), dim3(unsigned((segs + Geo::G - 1) / Geo::G)),      \
+                         dim3(Geo::NT), 0, st, static_cast<const C*>(y), static_cast<C*>(sx), pl->d_rows, \
+                         static_cast<const T*>(pl->d_tab[T_TILE]), hp.rows, row, int(segs), int(hp.half),  \
+                         static_cast<const C*>(pl->d_tw_out));                                         \
+      return true;                                                                                     \
+    }                                                                                                  \
+    return false;
+    QTAM_POW2_CASES(X)
+#undef X
+    default: return false;
+  }
 }
 
 enum Op { OP_FORWARD, OP_INVERSE, OP_FWD_ADJ, OP_INV_ADJ };
@@ -1874,7 +1958,7 @@ qtam_status qtam_plan_create(const qtam_params* params, qtam_plan_t* out) {
       (void)hipGetLastError();
       pl->num_cus = 1;
     }
-    pl->analytic_fwd = pl->hp.all_bisquare;
+    pl->analytic_fwd = pl->hp.all_bisquare && pl->hp.eps == 0.0;
     st = pl->hp.precision == QTAM_FP64 ? upload<double>(pl) : upload<float>(pl);
     if (st != QTAM_OK) {
       if (pl->dmem) (void)hipFree(pl->dmem);
@@ -1979,6 +2063,38 @@ qtam_status qtam_select_planes(qtam_plan_t pl, const void* y, const void* metric
                        reinterpret_cast<const uint4*>(ys), best + b0,
                        reinterpret_cast<uint4*>(static_cast<char*>(y_best) + size_t(b0) * size_t(units) * 16), units,
                        hp.planes);
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
+  }
+  return QTAM_OK;
+}
+
+qtam_status qtam_tile_inverse(qtam_plan_t pl, const void* y, int32_t row, void* x, int64_t batch, void* ws,
+                              size_t ws_bytes, qtam_stream_t stream) {
+  if (!pl || batch < 0 || row < 0 || row >= pl->hp.rows || !(pl->hp.eps > 0.0)) return QTAM_ERR_INVALID_ARG;
+  if (batch == 0) return QTAM_OK;
+  if (!y || !x || !ws) return QTAM_ERR_INVALID_ARG;
+  if (!pl->gpu_supported) return pl->unsupported_reason;
+  if (pl->big_rows || pl->bluestein) return QTAM_ERR_UNSUPPORTED;
+  if (!pl->device) return QTAM_ERR_INVALID_ARG;
+  const int64_t chunk = std::min<int64_t>(chunk_for(pl, batch, ws_bytes), 65535);
+  if (chunk < 1) return QTAM_ERR_WORKSPACE;
+  const HostPlan& hp = pl->hp;
+  const bool f64 = hp.precision == QTAM_FP64;
+  const size_t rb = f64 ? 8 : 4;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+    const int64_t segs = std::min(chunk, batch - b0);
+    const WsLayout lay = layout_for(pl, segs);
+    char* w = static_cast<char*>(ws);
+    const char* src = static_cast<const char*>(y) + size_t(b0) * size_t(hp.rows) * size_t(hp.n_out) * 2 * rb;
+    char* dst = static_cast<char*>(x) + size_t(b0) * size_t(hp.n) * rb;
+    void* sx = w + lay.pack;   // [segs][N/2 + 1], within the packed region (R (N/2 + 1) entries per segment)
+    const bool ok = f64 ? (launch_tile_rows<double>(pl, src, sx, row, segs, st) &&
+                           synthesize<double>(pl, sx, hp.half + 1, pl->d_one_start, pl->d_one_rows, dst, segs, w, lay, st))
+                        : (launch_tile_rows<float>(pl, src, sx, row, segs, st) &&
+                           synthesize<float>(pl, sx, hp.half + 1, pl->d_one_start, pl->d_one_rows, dst, segs, w, lay, st));
+    if (!ok) return QTAM_ERR_UNSUPPORTED;
     if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
   }
   return QTAM_OK;

@@ -83,6 +83,7 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
   }
   if (p.precision != QTAM_FP32 && p.precision != QTAM_FP64) return QTAM_ERR_INVALID_ARG;
   if (p.n_out < 0 || !(p.p_floor_rel >= 0.0) || p.p_floor_rel > 1.0) return QTAM_ERR_INVALID_ARG;
+  if (!(p.window_eps >= 0.0)) return QTAM_ERR_INVALID_ARG;
 
   hp = HostPlan();
   hp.fs = p.sample_rate;
@@ -92,6 +93,7 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
   hp.p_floor_rel = p.p_floor_rel;
   hp.window = planes[0].window;
   hp.window_param = planes[0].param;
+  hp.eps = p.window_eps;
   for (const Plane& pl : planes) hp.all_bisquare = hp.all_bisquare && pl.window == QTAM_WIN_BISQUARE;
   hp.n = n;
   hp.half = n / 2;
@@ -156,7 +158,9 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
     const int64_t s = static_cast<int64_t>(std::floor(f * T + 0.5));
     int64_t h = std::max<int64_t>(1, static_cast<int64_t>(std::ceil(f * T / plane.q)) / 2);
     if (hp.l_max > 0) h = std::max<int64_t>(1, std::min<int64_t>(h, hp.l_max / 2));
-    const int64_t a = std::max<int64_t>(0, s - h), b = std::min<int64_t>(hp.half, s + h);
+    // kept bins: the support clipped to 0..N/2, or the whole band with a stop band
+    const int64_t a = hp.eps > 0.0 ? 0 : std::max<int64_t>(0, s - h);
+    const int64_t b = hp.eps > 0.0 ? hp.half : std::min<int64_t>(hp.half, s + h);
     if (a > b || h > std::numeric_limits<int32_t>::max() / 4) return QTAM_ERR_INVALID_ARG;
     hp.centre[k] = static_cast<int32_t>(s);
     hp.half_width[k] = static_cast<int32_t>(h);
@@ -164,12 +168,14 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
     hp.hi[k] = static_cast<int32_t>(b);
     hp.offset[k] = hp.sum_len;
     hp.sum_len += b - a + 1;
-    longest = std::max(longest, 2 * h + 1);
+    longest = std::max(longest, hp.eps > 0.0 ? hp.half + 1 : 2 * h + 1);
 
     double e2 = 0.0;
     const size_t base = hp.win.size();
     for (int64_t c = a; c <= b; ++c) {
-      const double w = shape(plane.window, static_cast<double>(c - s) / static_cast<double>(h), plane.param);
+      const bool inside = c >= s - h && c <= s + h;
+      double w = inside ? shape(plane.window, static_cast<double>(c - s) / static_cast<double>(h), plane.param) : 0.0;
+      if (hp.eps > 0.0 && w == 0.0) w = hp.eps;   // the stop band, support end points included
       hp.win.push_back(w);
       e2 += w * w;
     }
@@ -228,6 +234,7 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
   hp.dual_tab.resize(hp.sum_len);
   hp.afwd_tab.resize(hp.sum_len);
   hp.ainv_tab.resize(hp.sum_len);
+  hp.tile_tab.assign(hp.sum_len, 0.0);
   for (int32_t k = 0; k < RT; ++k)
     for (int64_t c = hp.lo[k]; c <= hp.hi[k]; ++c) {
       const int64_t e = hp.offset[k] + (c - hp.lo[k]);
@@ -238,6 +245,7 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
       hp.dual_tab[e] = dual / nn;
       hp.afwd_tab[e] = w * fwd_scale * (edge ? 1.0 : 0.5);
       hp.ainv_tab[e] = dual * (edge ? 1.0 : 2.0) / nn;
+      if (hp.eps > 0.0) hp.tile_tab[e] = inv_scale / (w * nn);
     }
   return QTAM_OK;
 }

@@ -19,6 +19,7 @@ struct HostPlan {
   int32_t planes = 1;       // planes of a composite bank
   int32_t rows_per_plane = 0;
   bool all_bisquare = true; // every plane uses the bisquare window
+  double eps = 0.0;         // regularised stop-band value (0: plain windows)
   int32_t n_out = 0;        // N_out
   int32_t max_len = 0;      // max 2 h_k + 1
   int32_t precision = QTAM_FP32;
@@ -37,6 +38,7 @@ struct HostPlan {
   std::vector<double> dual_tab;   // inverse:  sqrt(N/N_out) * W * M / P / N
   std::vector<double> afwd_tab;   // adjoint of forward: fwd_tab * (1/2 inside, 1 at DC/Nyquist)
   std::vector<double> ainv_tab;   // adjoint of inverse: sqrt(N/N_out) W M / P * c_b / N, c = 2 inside
+  std::vector<double> tile_tab;   // single-tile recovery: sqrt(N/N_out) / W / N (eps > 0 only)
 
   // per bin
   std::vector<double> P;          // frame operator diagonal

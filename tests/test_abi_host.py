@@ -198,3 +198,22 @@ def test_composite_invalid_and_select_without_device():
     assert L.qtam_select_planes(gp._h, d, d, 0, d, None, d, 1, None) == binding.QTAM_ERR_INVALID_ARG
     assert L.qtam_select_planes(gp._h, d, d, 0, d, d, d, 1, None) == binding.QTAM_ERR_INVALID_ARG  # host-only
     assert L.qtam_select_planes(gp._h, d, d, 1, None, d, d, 0, None) == binding.QTAM_OK
+
+
+def test_regularised_plan_tables_match_oracle():
+    kw = dict(sample_rate=1024.0, n_samples=4096, q=8.0, f_min=10.0, f_max=400.0, n_rows=16)
+    for win, param in (("bisquare", 0.0), ("tukey", 0.5)):
+        gp = host_plan(window=win, window_param=param, window_eps=1e-5, **kw)
+        op = o.OraclePlan(fs=1024.0, n=4096, q=8.0, f_min=10.0, f_max=400.0, rows=16, window=WINS[win],
+                          window_param=param, eps=1e-5)
+        compare_tables(gp, op)
+        assert gp.info.max_len == 4096 // 2 + 1 and np.all(gp.windows_dense() > 0)
+    L = binding.lib
+    d = ctypes.c_void_p(0x1000)
+    plain = host_plan(**kw)
+    assert L.qtam_tile_inverse(plain._h, d, 0, d, 1, d, 1 << 20, None) == binding.QTAM_ERR_INVALID_ARG
+    reg = host_plan(window_eps=1e-5, **kw)
+    assert L.qtam_tile_inverse(reg._h, d, 16, d, 1, d, 1 << 20, None) == binding.QTAM_ERR_INVALID_ARG
+    assert L.qtam_tile_inverse(reg._h, d, 0, d, 0, d, 1 << 20, None) == binding.QTAM_OK
+    with pytest.raises(qt.QtamError):
+        host_plan(window_eps=-1.0, **kw)

@@ -1,0 +1,75 @@
+"""Regularised stop-band windows on the GPU (Sec. III; App. A): coefficients
+and canonical inverse against the oracle, and recovery of the signal from a
+single tile by spectral division.
+
+Bars: coefficients and canonical inverse as for plain plans (rel-L2 per
+segment FP32 <= 1e-5, FP64 <= 1e-12). Single-tile recovery divides by the
+window, so rounding is amplified by about max W / min W = 1/eps: the bar is
+2000 * u / eps with u the unit roundoff (FP32 eps = 1e-2: 1.2e-3; FP64
+eps = 1e-6: 2.2e-7), against the oracle's recovery from the same envelopes
+and, in FP64, against the signal itself.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import oracle as o
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "fp64": 1e-12}
+UNIT = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53}
+EPS = {"fp32": 1e-2, "fp64": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel_rows(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_regularised_forward_inverse_and_single_tile(torch_dev, precision):
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    fs, n, q, fmin, fmax, R, B = 1024.0, 4096, 8.0, 10.0, 400.0, 16, 3
+    eps = EPS[precision]
+    gp = qt.Plan(fs, n, q, fmin, fmax, R, precision=precision, window_eps=eps)
+    op = o.OraclePlan(fs=fs, n=n, q=q, f_min=fmin, f_max=fmax, rows=R, eps=eps)
+    assert gp.N_out == op.N_out == n
+    print("regularised", precision, "eps", eps, flush=True)
+    x = np.stack([synthetic.injected_segment(n, fs, synthetic.rng_for(15, i))[0] for i in range(B)])
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    cdt = torch.complex128 if precision == "fp64" else torch.complex64
+    xd = torch.from_numpy(x).to(dtype=dt, device="cuda")
+    xh = xd.double().cpu().numpy()
+    Yo = op.forward(xh)
+    Y = gp.forward(xd)
+    assert rel_rows(Y.cpu().numpy(), Yo).max() <= TOL[precision]
+    Yc = torch.from_numpy(Yo).to(dtype=cdt, device="cuda")
+    Ych = Yc.cpu().numpy().astype(np.complex128)
+    assert rel_rows(gp.inverse(Yc).cpu().numpy(), op.inverse(Ych)).max() <= TOL[precision]
+    bar = 2000.0 * UNIT[precision] / eps
+    for k in (0, R // 2, R - 1):
+        xt = gp.tile_inverse(Yc, k).cpu().numpy()
+        assert rel_rows(xt, op.tile_inverse(Ych, k)).max() <= bar, k
+        if precision == "fp64":
+            assert rel_rows(gp.tile_inverse(Y, k).cpu().numpy(), xh).max() <= bar, k
+
+
+def test_single_tile_needs_regularised_windows(torch_dev):
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    gp = qt.Plan(1024.0, 4096, 8.0, 10.0, 400.0, 16)
+    y = torch.zeros((1, 16, gp.N_out), dtype=torch.complex64, device="cuda")
+    with pytest.raises(qt.QtamError) as e:
+        gp.tile_inverse(y, 0)
+    assert e.value.status == 1
