@@ -171,6 +171,69 @@ __global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_rows_t(
   for (int i = 0; i < Geo::E; ++i) dst[n2_count * F::out_index(tl, i)] = v[i];
 }
 
+// Four-step second pass fused with the real-signal twist (k_twist below): the
+// output of row k2 at k1 (bin m = k2 + N2 k1 of Z) meets its mirror
+// N/2 - m in row N2 - k2 at N1 - 1 - k1 (row 0: itself at N1 - k1 mod N1), so
+// a workgroup takes mirrored row pairs: H = CC/2 rows j H + c and their
+// mirrors N2 - j H - c (workgroup 0: rows 0 .. H-1, N2/2 and N2-H+1 .. N2-1,
+// rows 0 and N2/2 being their own mirrors). After the row transforms the
+// values go through LDS to the thread that twists each bin.
+template <typename T, int L>
+__global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_spec_rows_twist(
+    const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out, int64_t n2,
+    int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw, Twiddle2<typename Complex<T>::type> tw2) {
+  using C = typename Complex<T>::type;
+  using Geo = ColGeom<T, L>;
+  using F = BlockFft<T, L, Geo::E, -1>;
+  constexpr int CC = Geo::CC, H = CC / 2;
+  static_assert(CC % 2 == 0, "paired rows");
+  __shared__ C lds[CC * lds_size(L)];
+  const int t = threadIdx.x;
+  const int64_t j = blockIdx.x;
+  auto row_of = [&](int c) -> int64_t {
+    if (j == 0) return c < H ? c : (c == H ? n2 / 2 : n2 - (c - H));
+    return c < H ? j * H + c : n2 - (j * H + (c - H));
+  };
+  const C* src = in + int64_t(blockIdx.y) * seg_stride;
+  for (int i = t; i < CC * L; i += Geo::NT) {
+    const int c = i / L;
+    lds[c * lds_size(L) + lds_pad(i % L)] = src[row_of(c) * L + (i % L)];
+  }
+  __syncthreads();
+  const int c = t % CC, tl = t / CC;
+  C* reg = lds + c * lds_size(L);
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) v[i] = reg[lds_pad(F::in_index(tl, i))];
+  __syncthreads();
+  F::run(v, reg, tl, F::twiddles(tw));
+  // every transform's output into its own LDS column, then the twist
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) reg[lds_pad(F::out_index(tl, i))] = v[i];
+  __syncthreads();
+  const int64_t r = row_of(c);
+  const int pc = (j == 0 && (c == 0 || c == H)) ? c : (c < H ? c + H : c - H);
+  const C* preg = lds + pc * lds_size(L);
+  C* dst = out + int64_t(blockIdx.y) * seg_stride;
+  const T hh = T(0.5);
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int k1 = F::out_index(tl, i);
+    const int64_t m = r + n2 * k1;
+    const C zp = v[i];
+    if (m == 0) {   // X[0] and X[N/2] share slot 0
+      dst[0] = C{zp.x + zp.y, zp.x - zp.y};
+      continue;
+    }
+    const int k1m = r == 0 ? (L - k1) & (L - 1) : L - 1 - k1;
+    const C zq = preg[lds_pad(k1m)];
+    const C w = tw2(m);                          // e^{-2 pi i m / N}
+    const C a = c_add(zp, c_conj(zq)), b = c_sub(zp, c_conj(zq));
+    const C xp = c_add(a, c_mul_si<-1>(c_mul(w, b)));
+    dst[m] = C{xp.x * hh, xp.y * hh};
+  }
+}
+
 // Real-signal spectrum from the N/2-point FFT Z of the even/odd pairs of a
 // segment, in place: for c in [0, N/2]
 //   X[c] = (Z[c] + Z*[N/2-c])/2 - (i/2) e^{-2 pi i c/N} (Z[c] - Z*[N/2-c])
@@ -1374,6 +1437,28 @@ bool launch_fft_rows_t(int log2l, const void* in, void* out, int64_t n2, int64_t
 }
 
 template <typename T>
+bool launch_spec_rows_twist(int log2l, const void* in, void* out, int64_t n2, int64_t segs, int64_t seg_stride,
+                            const void* tw, Twiddle2<typename Complex<T>::type> tw2, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  switch (log2l) {
+#define X(LG)                                                                                       \
+  case LG:                                                                                          \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                       \
+      using Geo = ColGeom<T, (1 << LG)>;                                                            \
+      if (n2 % Geo::CC) return false;                                                               \
+      hipLaunchKernelGGL((k_spec_rows_twist<T, (1 << LG)>), dim3(unsigned(n2 / Geo::CC), unsigned(segs)), \
+                         dim3(Geo::NT), 0, st, static_cast<const C*>(in), static_cast<C*>(out), n2,  \
+                         seg_stride, static_cast<const C*>(tw), tw2);                               \
+      return true;                                                                                  \
+    }                                                                                               \
+    return false;
+    QTAM_COL_CASES(X)
+#undef X
+    default: return false;
+  }
+}
+
+template <typename T>
 bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* out, const RowMeta* rows,
                  const void* roww, const void* tab, int R, int64_t total_rows, int64_t half, int64_t sum_len,
                  const void* tw, hipStream_t st, void* stats = nullptr) {
@@ -1593,7 +1678,20 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
   const int64_t half = hp.half;
   void* spec = ws + lay.spec;
   bool ok;
-  if (pl->radix_r == 1) {
+  bool twisted = false;
+  if (pl->radix_r == 1 && pl->four_step) {
+    // first pass, then the second pass with the real-signal twist folded in
+    void* tmp = ws + lay.tmp;
+    {
+      Timed tm(pl, K_SPEC1, st);
+      ok = launch_fft_cols<T, -1>(ilog2(pl->n2), x, tmp, pl->n1, segs, half, pl->d_tw_n2, tw2_of<T>(pl), st, 2);
+    }
+    if (ok) {
+      Timed tm(pl, K_SPEC2, st);
+      ok = launch_spec_rows_twist<T>(ilog2(pl->n1), tmp, spec, pl->n2, segs, half, pl->d_tw_n1, tw2_of<T>(pl), st);
+    }
+    twisted = true;
+  } else if (pl->radix_r == 1) {
     ok = transform_m2<T, -1>(pl, x, spec, ws + lay.tmp, segs, st, K_SPEC, K_SPEC1, K_SPEC2);
   } else {
     using C = typename Complex<T>::type;
@@ -1610,7 +1708,7 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
     if (ok) ok = launch_radix<T, -1>(pl, f, spec, segs, st);
   }
   if (!ok) return false;
-  {
+  if (!twisted) {
     using C = typename Complex<T>::type;
     Timed tm(pl, K_TWIST, st);
     hipLaunchKernelGGL((k_twist<T>), dim3(unsigned((half / 2 + 1 + 255) / 256), unsigned(segs)), dim3(256), 0, st,
