@@ -179,9 +179,7 @@ enum TwiddleMode { TW_POW = 0, TW_FULL = 1, TW_MIXED = 2 };
 constexpr int kFullStride = 16;
 constexpr bool tw_full_pass(int mode, int ns) { return mode == TW_FULL || (mode == TW_MIXED && ns <= kFullStride); }
 
-// PREFETCH: request the twiddles of the next pass before the LDS exchange
-// (more registers live across the barrier) instead of after it.
-template <typename T, int L, int E, int S, int TW = TW_POW, bool PREFETCH = false>
+template <typename T, int L, int E, int S, int TW = TW_POW>
 struct BlockFft {
   using C = typename Complex<T>::type;
   static_assert((L & (L - 1)) == 0 && (E & (E - 1)) == 0 && E <= L && E <= 16, "pow2 sizes");
@@ -250,13 +248,13 @@ struct BlockFft {
     }
   }
 
-  // One radix-R pass on registers (twiddles w already loaded for NS > 1),
-  // then, unless it was the last, the next pass's twiddles are requested and
-  // the values exchanged through LDS while they arrive.
+  // One radix-R pass on registers: for NS > 1 its twiddles are read and
+  // applied, then the butterflies; unless it was the last pass the values
+  // are exchanged through LDS into the next pass's order.
   template <int NS>
   __device__ static __forceinline__ void pass(C (&v)[E], C (&w)[E], C* lds, int tl, rsrc_t tw) {
     constexpr int R = radix(NS);
-    if constexpr (!PREFETCH && NS > 1) load_twiddles<NS>(w, tl, tw);
+    if constexpr (NS > 1) load_twiddles<NS>(w, tl, tw);
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
       if constexpr (NS > 1) {
@@ -272,7 +270,6 @@ struct BlockFft {
     if constexpr (NS * R < L) {
       constexpr int NS2 = NS * R;
       constexpr int R2 = radix(NS2);
-      if constexpr (PREFETCH) load_twiddles<NS2>(w, tl, tw);
 #pragma unroll
       for (int q = 0; q < E / R; ++q) {
         const int j = tl + q * TPR;
