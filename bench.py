@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--hbm-budget-gb", type=float, default=32.0, help="serving: device memory budget")
     ap.add_argument("--sweep", default="1000,5000,20000", help="serving: extra arrival rates for the saturation sweep")
     ap.add_argument("--no-composite", action="store_true", help="skip the composite-bank leg")
+    ap.add_argument("--separate-plans", action="store_true",
+                    help="time each plan's own forward (its own spectrum) instead of the forward sweep")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the short timing of the other forward form (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of 1 GiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -150,14 +154,24 @@ def main():
     assert all(p.N_out == n_out for p in plans)
     ws_bytes = max(p.workspace_bytes(B) for p in plans)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    y = torch.empty((B, W["rows"], n_out), dtype=torch.complex128 if b == 8 else torch.complex64, device=dev)
+    cdt = torch.complex128 if b == 8 else torch.complex64
+    ys = [torch.empty((B, W["rows"], n_out), dtype=cdt, device=dev) for _ in plans]
     xr = torch.empty_like(x)
     stream = torch.cuda.current_stream(dev)
 
-    def step():
-        for p in plans:
+    def step_sweep():
+        # the Q set as one sweep: each segment's spectrum once, every plan's rows from it
+        qt.forward_sweep(plans, x, outs=ys, ws=ws, stream=stream)
+        for p, y in zip(plans, ys):
+            p.inverse(y, out=xr, ws=ws, stream=stream)
+
+    def step_separate():
+        for p, y in zip(plans, ys):
             p.forward(x, out=y, ws=ws, stream=stream)
             p.inverse(y, out=xr, ws=ws, stream=stream)
+
+    step, other = (step_separate, step_sweep) if args.separate_plans else (step_sweep, step_separate)
+    form = "separate plans" if args.separate_plans else "forward sweep"
 
     for _ in range(args.warmup):
         step()
@@ -177,9 +191,26 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     print("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
 
-    # whole-path roofline: algorithmic bytes 2 b N + 4 b R N_out per segment and plan
-    alg_path = len(plans) * B * (2 * b * W["n"] + 4 * b * W["rows"] * n_out)
+    # whole-path roofline, algorithmic bytes per segment: each plan writes and
+    # reads its envelopes (4 b R N_out) and writes a reconstruction (b N); the
+    # signal is read once by the sweep, once per plan by separate plans
+    reads_x = len(plans) if args.separate_plans else 1
+    alg_path = B * (reads_x * b * W["n"] + len(plans) * (b * W["n"] + 4 * b * W["rows"] * n_out))
     path_gbs = alg_path / (ms_per_step * 1e-3) / 1e9
+
+    # the other forward form, briefly, for comparison
+    compare = None
+    if not args.no_compare:
+        for _ in range(3):
+            other()
+        torch.cuda.synchronize()
+        reps = max(5, min(10, args.steps))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            other()
+        torch.cuda.synchronize()
+        compare = {"form": "forward sweep" if args.separate_plans else "separate plans",
+                   "ms_per_step": 1e3 * (time.perf_counter() - t0) / reps, "steps": reps}
 
     # per-kernel durations with HIP events on the launch stream
     kernels = {}
@@ -238,8 +269,12 @@ def main():
         "dtype": "f64" if b == 8 else "f32",
         "data": "synthetic",
         "config": {"workload": "batched QTAM fwd+inv: %d segments x %d samples @ %g Hz, coloured noise + "
-                               "chirp + 2 sine-Gaussians; Q in %s (one plan each), %d rows %g-%g Hz, N_out %d"
-                               % (B, W["n"], W["fs"], list(W["qs"]), W["rows"], W["f_min"], W["f_max"], n_out),
+                               "chirp + 2 sine-Gaussians; Q in %s (one plan each, %s), %d rows %g-%g Hz, N_out %d"
+                               % (B, W["n"], W["fs"], list(W["qs"]),
+                                  "each with its own spectrum" if args.separate_plans
+                                  else "forward as one sweep over a shared spectrum",
+                                  W["rows"], W["f_min"], W["f_max"], n_out),
+                   "form": form,
                    "batch": B, "n_samples": W["n"], "fs": W["fs"], "q": list(W["qs"]), "rows": W["rows"],
                    "f_min": W["f_min"], "f_max": W["f_max"], "n_out": n_out, "precision": args.precision},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -250,6 +285,7 @@ def main():
         "kernels": {n: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in k.items()}
                     for n, k in kernels.items()},
         "roofline": roofline,
+        "other_form": compare,
     }
 
     if not args.no_composite:
@@ -260,7 +296,7 @@ def main():
     return 0
 
 
-def composite_leg(args, x, B, W, ms_three_plans):
+def composite_leg(args, x, B, W, ms_main):
     """The same Q set as one composite bank (one spectrum, one launch per
     kernel, the frame summed over all 3 R rows): forward with row statistics,
     per-segment best plane by energy, inverse from the whole bank."""
@@ -293,7 +329,7 @@ def composite_leg(args, x, B, W, ms_three_plans):
     del y, m, ws
     return {"rows": p.R, "planes": p.planes, "ms_per_step": ms,
             "samples_per_s": len(W["qs"]) * B * W["n"] / (ms * 1e-3),
-            "vs_separate_plans": ms_three_plans / ms, "best_plane_counts": counts,
+            "speed_vs_main_step": ms_main / ms, "best_plane_counts": counts,
             "what": "forward with row statistics + energy selection + inverse of one %d-row bank "
                     "(Q %s), samples counted once per plane" % (p.R, list(W["qs"]))}
 

@@ -200,6 +200,21 @@ size_t qtam_dense_workspace_size(qtam_plan_t plan, int64_t batch);
 qtam_status qtam_dense(qtam_plan_t plan, const void* y, void* dense, int64_t batch,
                        void* ws, size_t ws_bytes, qtam_stream_t stream);
 
+/* Forward transform of one batch under several plans at once (the multi-Q
+ * extension of App. A, where every configuration of the bank works from the
+ * same spectrum): the real spectrum of each segment is computed once and
+ * every plan's rows are taken from it. plans[0 .. n_plans-1] must share N
+ * and the precision (else QTAM_ERR_INVALID_ARG) and may differ in anything
+ * else (Q, rows, band, window, N_out). x [batch, N] real; y[i] is plan i's
+ * output [batch, R_i, N_out_i] complex, exactly as qtam_forward(plans[i], ...)
+ * writes it (the same kernels on the same spectrum: identical bits). ws must
+ * hold qtam_workspace_size of every plan for one segment at least; with less
+ * than the largest of them for the whole batch, the batch runs in chunks. All
+ * pointers are device pointers except plans and y, which are host arrays of
+ * n_plans entries. Work is enqueued on `stream`; errors as qtam_forward.     */
+qtam_status qtam_forward_sweep(const qtam_plan_t* plans, int32_t n_plans, const void* x, void* const* y,
+                               int64_t batch, void* ws, size_t ws_bytes, qtam_stream_t stream);
+
 /* Plane metrics (the per-plane quality metric of the multi-Q extension,
  * App. A): which statistic of a plane scores it.                           */
 typedef enum { QTAM_METRIC_ENERGY = 0,   /* sum over the plane's rows and m of |Y|^2 */

@@ -7,6 +7,6 @@ device tensors. Importing this package loads libqtam.so and fails if it has not
 been built (``python paper_2603_29785_amd/build.py``); there is no CPU fallback.
 """
 from .binding import (Plan, PlanInfo, QtamError, lib, status_string, version, EXPORTED,  # noqa: F401
-                      FP32, FP64)
+                      FP32, FP64, forward_sweep)
 
-__all__ = ["Plan", "PlanInfo", "QtamError", "status_string", "version", "FP32", "FP64"]
+__all__ = ["Plan", "PlanInfo", "QtamError", "status_string", "version", "FP32", "FP64", "forward_sweep"]

@@ -94,6 +94,7 @@ EXPORTED = [
     "qtam_forward", "qtam_inverse", "qtam_forward_adjoint", "qtam_inverse_adjoint",
     "qtam_forward_metric", "qtam_select_planes", "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string",
     "qtam_dense", "qtam_dense_workspace_size", "qtam_tile_inverse", "qtam_last_error", "qtam_version",
+    "qtam_forward_sweep",
 ]
 
 
@@ -124,6 +125,8 @@ def _load():
     L.qtam_dense.restype = ctypes.c_int
     L.qtam_dense_workspace_size.argtypes = [vp, i64]
     L.qtam_dense_workspace_size.restype = sz
+    L.qtam_forward_sweep.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, vp, ctypes.POINTER(vp), i64, vp, sz, vp]
+    L.qtam_forward_sweep.restype = ctypes.c_int
     L.qtam_forward_metric.argtypes = [vp, vp, vp, vp, i64, vp, sz, vp]
     L.qtam_forward_metric.restype = ctypes.c_int
     L.qtam_select_planes.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, i64, vp]
@@ -252,11 +255,13 @@ class Plan:
         self.host_only = host_only
         self._ws = None
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.qtam_plan_destroy):
+        # the library function is bound at definition time: at interpreter exit
+        # the module's globals may already be gone when a plan is collected
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib.qtam_plan_destroy(h)
-            self._h = ctypes.c_void_p()
+            _destroy(h)
+            h.value = None
 
     # ------------------------------------------------------------------ sizes
     @property
@@ -482,3 +487,40 @@ class Plan:
         got = ctypes.c_int32()
         _check(lib.qtam_timing_collect(self._h, names, ms, cnt, n, ctypes.byref(got)), "qtam_timing_collect")
         return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(n, got.value))}
+
+
+def forward_sweep(plans, x, outs=None, ws=None, stream=None):
+    """Forward transform of x [..., N] under every plan in `plans` (same N and
+    precision), with the spectrum of each segment computed once for all of
+    them (multi-Q extension, App. A). Returns one Y [..., R_i, N_out_i] per
+    plan, identical to ``plans[i].forward(x)``."""
+    import torch
+    plans = list(plans)
+    if not plans:
+        raise ValueError("forward_sweep needs at least one plan")
+    x = plans[0]._check_signal(x)
+    lead = x.shape[:-1]
+    batch = int(np.prod(lead)) if len(lead) else 1
+    if outs is None:
+        outs = [torch.empty(tuple(lead) + (p.R, p.N_out), dtype=p._complex_dtype(), device=x.device)
+                for p in plans]
+    outs = list(outs)
+    if len(outs) != len(plans):
+        raise ValueError("one output per plan")
+    for p, y in zip(plans, outs):
+        if (y.dtype != p._complex_dtype() or tuple(y.shape) != tuple(lead) + (p.R, p.N_out)
+                or not y.is_contiguous() or y.device != x.device):
+            raise ValueError("output of plan with R=%d, N_out=%d must be a contiguous %s %s on %s" % (
+                p.R, p.N_out, p._complex_dtype(), tuple(lead) + (p.R, p.N_out), x.device))
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    if ws is None:
+        need = max(p.workspace_bytes(batch) for p in plans)
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    n = len(plans)
+    hs = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+    ys = (ctypes.c_void_p * n)(*[y.data_ptr() for y in outs])
+    _check(lib.qtam_forward_sweep(hs, n, ctypes.c_void_p(x.data_ptr()), ys, int(batch),
+                                  ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * ws.element_size()),
+                                  ctypes.c_void_p(stream.cuda_stream)), "qtam_forward_sweep")
+    return outs

@@ -1670,10 +1670,12 @@ bool launch_radix(qtam_plan_s* pl, const void* in, void* out, int64_t segs, hipS
   return true;
 }
 
-// analysis: real signal x -> rows (forward with T_FWD, inverse adjoint with T_AINV)
+// analysis, first half: real signal x -> its spectrum in ws + lay.spec (bins
+// 0 .. N/2 - 1 of the N/2-point half-size transform after the real-signal twist).
+// Depends on N and the precision only, so plans that share both share it.
 template <typename T>
-bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t segs, char* ws,
-                  const WsLayout& lay, hipStream_t st, void* stats) {
+bool analysis_spectrum(qtam_plan_s* pl, const void* x, int64_t segs, char* ws, const WsLayout& lay,
+                       hipStream_t st) {
   const HostPlan& hp = pl->hp;
   const int64_t half = hp.half;
   void* spec = ws + lay.spec;
@@ -1714,6 +1716,17 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
     hipLaunchKernelGGL((k_twist<T>), dim3(unsigned((half / 2 + 1 + 255) / 256), unsigned(segs)), dim3(256), 0, st,
                        static_cast<C*>(spec), half, tw2_of<T>(pl));
   }
+  return true;
+}
+
+// analysis, second half: spectrum -> rows (forward with T_FWD, inverse adjoint
+// with T_AINV). Reads ws + lay.spec, writes y (and ws + lay.rows for long rows).
+template <typename T>
+bool analysis_rows(qtam_plan_s* pl, int table, void* y, int64_t segs, char* ws, const WsLayout& lay,
+                   hipStream_t st, void* stats) {
+  const HostPlan& hp = pl->hp;
+  const int64_t half = hp.half;
+  void* spec = ws + lay.spec;
   if (pl->big_rows) {
     using C = typename Complex<T>::type;
     const Twiddle2<C> twr{static_cast<const C*>(pl->d_twr_fine), static_cast<const C*>(pl->d_twr_coarse),
@@ -1758,6 +1771,12 @@ bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t se
                         pl->d_tw_out, st, stats);
 }
 
+template <typename T>
+bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t segs, char* ws,
+                  const WsLayout& lay, hipStream_t st, void* stats) {
+  return analysis_spectrum<T>(pl, x, segs, ws, lay, st) && analysis_rows<T>(pl, table, y, segs, ws, lay, st, stats);
+}
+
 // synthesis: rows -> real signal (inverse with T_DUAL, forward adjoint with T_AFWD)
 template <typename T>
 bool inverse_rows(qtam_plan_s* pl, int table, const void* y, int64_t segs, char* ws, const WsLayout& lay,
@@ -1799,10 +1818,7 @@ bool synthesize(qtam_plan_s* pl, const void* pack, int64_t slen, const int* star
 template <typename T>
 bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t segs, char* ws,
                    const WsLayout& lay, hipStream_t st) {
-  using C = typename Complex<T>::type;
   const HostPlan& hp = pl->hp;
-  const int64_t half = hp.half;
-  void* spec = ws + lay.spec;
   void* pack = ws + lay.pack;
   bool ok = inverse_rows<T>(pl, table, y, segs, ws, lay, st);
   if (!ok) return false;
@@ -2124,6 +2140,54 @@ qtam_status qtam_forward_metric(qtam_plan_t pl, const void* x, void* y, void* me
                                 size_t ws_bytes, qtam_stream_t stream) {
   if (batch > 0 && !metric) return QTAM_ERR_INVALID_ARG;
   return run_op(pl, OP_FORWARD, x, y, batch, ws, ws_bytes, stream, metric);
+}
+
+qtam_status qtam_forward_sweep(const qtam_plan_t* plans, int32_t n_plans, const void* x, void* const* y,
+                               int64_t batch, void* ws, size_t ws_bytes, qtam_stream_t stream) {
+  if (!plans || n_plans < 1 || batch < 0) return QTAM_ERR_INVALID_ARG;
+  for (int32_t i = 0; i < n_plans; ++i)
+    if (!plans[i]) return QTAM_ERR_INVALID_ARG;
+  const qtam_plan_s* p0 = plans[0];
+  for (int32_t i = 0; i < n_plans; ++i) {
+    const qtam_plan_s* p = plans[i];
+    if (p->hp.n != p0->hp.n || p->hp.precision != p0->hp.precision) return QTAM_ERR_INVALID_ARG;
+  }
+  if (batch == 0) return QTAM_OK;
+  if (!x || !y || !ws) return QTAM_ERR_INVALID_ARG;
+  int64_t chunk = 65535;
+  for (int32_t i = 0; i < n_plans; ++i) {
+    const qtam_plan_s* p = plans[i];
+    if (!y[i]) return QTAM_ERR_INVALID_ARG;
+    if (!p->gpu_supported) return p->unsupported_reason;
+    if (!p->device || p->device_id != p0->device_id) return QTAM_ERR_INVALID_ARG;
+    chunk = std::min(chunk, chunk_for(p, batch, ws_bytes));
+  }
+  if (chunk < 1) return QTAM_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool f64 = p0->hp.precision == QTAM_FP64;
+  const size_t rb = f64 ? 8 : 4;
+  (void)hipGetLastError();
+  for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+    const int64_t segs = std::min(chunk, batch - b0);
+    const char* src = static_cast<const char*>(x) + size_t(b0) * size_t(p0->hp.n) * rb;
+    // the spectrum sits at the start of every plan's workspace layout, with the
+    // same size, so the first plan computes it and every plan reads it
+    qtam_plan_s* first = plans[0];
+    const WsLayout lay0 = layout_for(first, segs);
+    bool ok = f64 ? analysis_spectrum<double>(first, src, segs, static_cast<char*>(ws), lay0, st)
+                  : analysis_spectrum<float>(first, src, segs, static_cast<char*>(ws), lay0, st);
+    for (int32_t i = 0; ok && i < n_plans; ++i) {
+      qtam_plan_s* p = plans[i];
+      const WsLayout lay = layout_for(p, segs);
+      const size_t y_seg = size_t(p->hp.rows) * size_t(p->hp.n_out) * 2 * rb;
+      char* dst = static_cast<char*>(y[i]) + size_t(b0) * y_seg;
+      ok = f64 ? analysis_rows<double>(p, T_FWD, dst, segs, static_cast<char*>(ws), lay, st, nullptr)
+               : analysis_rows<float>(p, T_FWD, dst, segs, static_cast<char*>(ws), lay, st, nullptr);
+    }
+    if (!ok) return QTAM_ERR_UNSUPPORTED;
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
+  }
+  return QTAM_OK;
 }
 
 qtam_status qtam_select_planes(qtam_plan_t pl, const void* y, const void* metric, int32_t kind, void* score,

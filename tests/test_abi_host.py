@@ -143,6 +143,33 @@ def test_calls_without_device_return_status():
     L.qtam_plan_destroy(None)
 
 
+def test_forward_sweep_validation_without_device():
+    a = host_plan(sample_rate=1024.0, n_samples=4096, q=4.0, f_min=10.0, f_max=400.0, n_rows=16)
+    b = host_plan(sample_rate=1024.0, n_samples=4096, q=16.0, f_min=20.0, f_max=300.0, n_rows=9)
+    other_n = host_plan(sample_rate=1024.0, n_samples=8192, q=4.0, f_min=10.0, f_max=400.0, n_rows=16)
+    other_p = host_plan(sample_rate=1024.0, n_samples=4096, q=4.0, f_min=10.0, f_max=400.0, n_rows=16,
+                        precision=binding.FP64)
+    L = binding.lib
+    d = ctypes.c_void_p(0x1000)   # never dereferenced: the call fails validation first
+    ws = max(a.workspace_bytes(1), b.workspace_bytes(1))
+
+    def call(plans, batch, ys=None, x=d):
+        n = len(plans)
+        hs = (ctypes.c_void_p * max(n, 1))(*[p._h.value for p in plans])
+        ys = (ctypes.c_void_p * max(n, 1))(*([d.value] * n if ys is None else ys))
+        return L.qtam_forward_sweep(hs, n, x, ys, batch, d, ws, None)
+
+    assert call([a, b], 0) == binding.QTAM_OK                                  # empty batch
+    assert call([a, b], 1) == binding.QTAM_ERR_INVALID_ARG                     # host-only plans
+    assert call([a, other_n], 0) == binding.QTAM_ERR_INVALID_ARG               # N differs
+    assert call([a, other_p], 0) == binding.QTAM_ERR_INVALID_ARG               # precision differs
+    assert call([], 1) == binding.QTAM_ERR_INVALID_ARG                         # no plans
+    assert call([a, b], 1, ys=[d.value, None]) == binding.QTAM_ERR_INVALID_ARG  # missing output
+    assert call([a, b], 1, x=None) == binding.QTAM_ERR_INVALID_ARG
+    assert call([a, b], -1) == binding.QTAM_ERR_INVALID_ARG
+    assert L.qtam_forward_sweep(None, 1, d, None, 1, d, ws, None) == binding.QTAM_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("fs,n,odd_n_out", [(4096.0, 2 * 7 * 1024, False), (16384.0, 1 << 20, True)])
 def test_unsupported_shapes_report_unsupported_not_invalid(fs, n, odd_n_out):
     """N/2 with an odd factor other than 3 or 5, or a non-power-of-two N_out

@@ -1,0 +1,108 @@
+"""Forward sweep on the GPU (multi-Q extension, App. A): several plans over one
+batch with the spectrum computed once. Each plan's output must be identical
+(bit for bit) to that plan's own forward call, which the parity tests tie to
+the oracle; one case is also checked against the oracle directly (rel-L2 per
+segment FP32 <= 1e-5, FP64 <= 1e-12)."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import oracle as o
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "fp64": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel_rows(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+# (fs, N, batch, plan list [(Q, f_min, f_max, R, n_out)]) ; n_out -1 = odd max_len (chirp-z rows)
+CASES = {
+    "q_set_N16384": (4096.0, 16384, 5, [(4.0, 20.0, 1000.0, 64, 0), (8.0, 20.0, 1000.0, 64, 0),
+                                         (16.0, 20.0, 1000.0, 64, 0)]),
+    "q_set_N131072_four_step": (4096.0, 131072, 3, [(4.0, 10.0, 2048.0, 256, 0), (8.0, 10.0, 2048.0, 256, 0),
+                                                   (16.0, 10.0, 2048.0, 256, 0)]),
+    "mixed_shapes_radix3": (4096.0, 24576, 4, [(8.0, 20.0, 1000.0, 16, 0), (12.0, 40.0, 1500.0, 40, 0),
+                                               (6.0, 20.0, 800.0, 24, -1)]),
+    "long_rows_and_short": (16384.0, 1 << 20, 1, [(8.0, 20.0, 4000.0, 64, 0), (8.0, 20.0, 4000.0, 512, 0)]),
+}
+
+
+def make_plans(qt, fs, n, specs, precision):
+    plans = []
+    for q, fmin, fmax, R, n_out in specs:
+        if n_out < 0:
+            n_out = qt.Plan(fs, n, q, fmin, fmax, R, host_only=True).info.max_len | 1
+        plans.append(qt.Plan(fs, n, q, fmin, fmax, R, precision=precision, n_out=n_out))
+    return plans
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_sweep_equals_each_plans_forward(torch_dev, name, precision):
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    fs, n, B, specs = CASES[name]
+    if name == "long_rows_and_short" and precision == "fp64":
+        B = 1
+    print("sweep", name, precision, flush=True)
+    plans = make_plans(qt, fs, n, specs, precision)
+    if name == "long_rows_and_short":
+        assert plans[0].N_out > 8192          # rows longer than one workgroup's transform
+    if name == "mixed_shapes_radix3":
+        assert plans[2].N_out % 2 == 1
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    x = torch.from_numpy(synthetic.batched_segments(B, n, fs, dtype=np.float64)).to(dtype=dt, device="cuda")
+    ys = qt.forward_sweep(plans, x)
+    for p, y in zip(plans, ys):
+        assert torch.equal(y, p.forward(x)), (p.R, p.N_out)
+    # the chunked form (workspace for one segment) gives the same bits
+    ws = torch.empty(max(p.workspace_bytes(1) for p in plans), dtype=torch.uint8, device="cuda")
+    outs = [torch.full_like(y, float("nan")) for y in ys]
+    qt.forward_sweep(plans, x, outs=outs, ws=ws)
+    for y, z in zip(ys, outs):
+        assert torch.equal(y, z)
+
+
+def test_sweep_against_oracle(torch_dev):
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    fs, n, B, specs = CASES["q_set_N16384"]
+    plans = make_plans(qt, fs, n, specs, "fp32")
+    x = torch.from_numpy(synthetic.batched_segments(B, n, fs, dtype=np.float64)).float().cuda()
+    ys = qt.forward_sweep(plans, x)
+    xh = x.double().cpu().numpy()
+    for (q, fmin, fmax, R, _), y in zip(specs, ys):
+        op = o.OraclePlan(fs=fs, n=n, q=q, f_min=fmin, f_max=fmax, rows=R)
+        assert rel_rows(y.cpu().numpy(), op.forward(xh)).max() <= TOL["fp32"]
+
+
+def test_sweep_errors_and_empty(torch_dev):
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    a = qt.Plan(1024.0, 4096, 4.0, 10.0, 400.0, 16)
+    b = qt.Plan(1024.0, 8192, 4.0, 10.0, 400.0, 16)
+    c = qt.Plan(1024.0, 4096, 4.0, 10.0, 400.0, 16, precision="fp64")
+    x = torch.zeros((2, 4096), dtype=torch.float32, device="cuda")
+    for bad in ([a, b], [a, c]):          # N differs; precision differs
+        outs = [torch.empty((2, p.R, p.N_out), dtype=torch.complex128 if p.fp64 else torch.complex64,
+                            device="cuda") for p in bad]
+        with pytest.raises(qt.QtamError) as e:
+            qt.forward_sweep(bad, x, outs=outs)
+        assert e.value.status == 1
+    ys = qt.forward_sweep([a], torch.zeros((0, 4096), dtype=torch.float32, device="cuda"))
+    assert ys[0].shape == (0, 16, a.N_out)
+    with pytest.raises(ValueError):
+        qt.forward_sweep([], x)
