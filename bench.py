@@ -122,8 +122,9 @@ def kernel_bytes(kind: str, plan, batch: int, b: int) -> float:
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the transform shards by segment with no exchange, "
-              "and this build runs on a single MI355X; use --gpus 1", file=sys.stderr)
+        print("bench.py times one GPU only: segments shard across GPUs with no exchange, so each "
+              "GPU's share is this same single-GPU run; multi-GPU runs are not supported, use --gpus 1",
+              file=sys.stderr)
         return 2
     if args.serving:
         return serving_main(args)
