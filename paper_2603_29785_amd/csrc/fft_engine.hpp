@@ -105,6 +105,83 @@ __device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
   a3 = c_sub(t1, t3);
 }
 
+// Second half of a radix-16 DFT split as n = 4 n1 + n2: group n2's output
+// k1 sits at a[4 k1 + n2]; twiddles exp(S 2 pi i n2 k1 / 16), then the outer
+// length-4 DFTs over the groups, results in natural order.
+template <int S, typename C>
+__device__ __forceinline__ void dft16_outer(C* a) {
+  a[5] = c_mul_root16<S, 1>(a[5]);
+  a[9] = c_mul_root16<S, 2>(a[9]);
+  a[13] = c_mul_root16<S, 3>(a[13]);
+  a[6] = c_mul_root16<S, 2>(a[6]);
+  a[10] = c_mul_root16<S, 4>(a[10]);
+  a[14] = c_mul_root16<S, 6>(a[14]);
+  a[7] = c_mul_root16<S, 3>(a[7]);
+  a[11] = c_mul_root16<S, 6>(a[11]);
+  a[15] = c_mul_root16<S, 9>(a[15]);
+  C y[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    C b0 = a[4 * k1], b1 = a[4 * k1 + 1], b2 = a[4 * k1 + 2], b3 = a[4 * k1 + 3];
+    dft4<S>(b0, b1, b2, b3);
+    y[k1] = b0;
+    y[k1 + 4] = b1;
+    y[k1 + 8] = b2;
+    y[k1 + 12] = b3;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a[i] = y[i];
+}
+
+// Radix-16 DFT of inputs known to be zero except a[0], a[1], a[14], a[15]
+// (NZ = 4) or a[0], a[15] (NZ = 2): the operations of dft_small<S, 16> on the
+// non-zero terms only, in the same order, so the results are the same bits
+// (up to the sign of zeros). Each inner length-4 DFT then has one non-zero
+// input: at n1 = 0 it copies it to all four outputs; at n1 = 3 the outputs
+// are x, S i (-x), -x, -(S i (-x)).
+template <int S, int NZ, typename C>
+__device__ __forceinline__ void dft16_sparse(C* a) {
+  static_assert(NZ == 2 || NZ == 4, "two or four non-zero inputs");
+  auto from_first = [&](int n2) {   // group n2 with its only input at n1 = 0
+    a[n2 + 4] = a[n2];
+    a[n2 + 8] = a[n2];
+    a[n2 + 12] = a[n2];
+  };
+  auto from_last = [&](int n2) {    // group n2 with its only input at n1 = 3
+    const C x = a[n2 + 12];
+    const C r = c_mul_si<S>(C{-x.x, -x.y});
+    a[n2] = x;
+    a[n2 + 4] = r;
+    a[n2 + 8] = C{-x.x, -x.y};
+    a[n2 + 12] = C{-r.x, -r.y};
+  };
+  from_first(0);
+  from_last(3);
+  if constexpr (NZ == 4) {
+    from_first(1);
+    from_last(2);
+    dft16_outer<S>(a);
+  } else {
+    // groups 1 and 2 are zero: twiddles only on group 3, and each outer
+    // length-4 DFT sees (b0, 0, 0, b3)
+    a[7] = c_mul_root16<S, 3>(a[7]);
+    a[11] = c_mul_root16<S, 6>(a[11]);
+    a[15] = c_mul_root16<S, 9>(a[15]);
+    C y[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      const C b0 = a[4 * k1], b3 = a[4 * k1 + 3];
+      const C t3 = c_mul_si<S>(C{-b3.x, -b3.y});
+      y[k1] = c_add(b0, b3);
+      y[k1 + 4] = c_add(b0, t3);
+      y[k1 + 8] = c_sub(b0, b3);
+      y[k1 + 12] = c_sub(b0, t3);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = y[i];
+  }
+}
+
 // In-register DFT of R values in natural order (R in 1, 2, 4, 8, 16).
 // R = 8 and 16 split as n = 4 n1 + n2 ... : inner radix-4 DFTs over strided
 // groups, twiddles exp(S 2 pi i n2 k1 / R), outer DFTs over the groups.
@@ -138,28 +215,7 @@ __device__ __forceinline__ void dft_small(C* a) {
     dft4<S>(a[1], a[5], a[9], a[13]);
     dft4<S>(a[2], a[6], a[10], a[14]);
     dft4<S>(a[3], a[7], a[11], a[15]);
-    // group n2, output k1 sits at a[4 k1 + n2]; twiddle exp(S 2 pi i n2 k1/16)
-    a[5] = c_mul_root16<S, 1>(a[5]);
-    a[9] = c_mul_root16<S, 2>(a[9]);
-    a[13] = c_mul_root16<S, 3>(a[13]);
-    a[6] = c_mul_root16<S, 2>(a[6]);
-    a[10] = c_mul_root16<S, 4>(a[10]);
-    a[14] = c_mul_root16<S, 6>(a[14]);
-    a[7] = c_mul_root16<S, 3>(a[7]);
-    a[11] = c_mul_root16<S, 6>(a[11]);
-    a[15] = c_mul_root16<S, 9>(a[15]);
-    C y[16];
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) {
-      C b0 = a[4 * k1], b1 = a[4 * k1 + 1], b2 = a[4 * k1 + 2], b3 = a[4 * k1 + 3];
-      dft4<S>(b0, b1, b2, b3);
-      y[k1] = b0;
-      y[k1 + 4] = b1;
-      y[k1 + 8] = b2;
-      y[k1 + 12] = b3;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) a[i] = y[i];
+    dft16_outer<S>(a);
   }
 }
 
@@ -252,7 +308,7 @@ struct BlockFft {
   // applied, then the butterflies; unless it was the last pass the values
   // are exchanged through LDS into the next pass's order.
   template <int NS>
-  __device__ static __forceinline__ void pass(C (&v)[E], C (&w)[E], C* lds, int tl, rsrc_t tw) {
+  __device__ static __forceinline__ void pass(C (&v)[E], C (&w)[E], C* lds, int tl, rsrc_t tw, int nz) {
     constexpr int R = radix(NS);
     if constexpr (NS > 1) load_twiddles<NS>(w, tl, tw);
 #pragma unroll
@@ -265,7 +321,13 @@ struct BlockFft {
           v[q * R + r] = c_mul(v[q * R + r], t);
         }
       }
-      dft_small<S, R>(&v[q * R]);
+      if constexpr (NS == 1 && R == 16) {
+        if (nz == 2) dft16_sparse<S, 2>(&v[q * R]);
+        else if (nz == 4) dft16_sparse<S, 4>(&v[q * R]);
+        else dft_small<S, R>(&v[q * R]);
+      } else {
+        dft_small<S, R>(&v[q * R]);
+      }
     }
     if constexpr (NS * R < L) {
       constexpr int NS2 = NS * R;
@@ -286,15 +348,19 @@ struct BlockFft {
         for (int r = 0; r < R2; ++r) v[q * R2 + r] = lds[lds_pad(j + r * (L / R2))];
       }
       __syncthreads();
-      pass<NS2>(v, w, lds, tl, tw);
+      pass<NS2>(v, w, lds, tl, tw, 0);
     }
   }
 
   // Every thread of the workgroup must call run (it contains barriers).
   // tw: buffer resource over the per-pass twiddle table of this (L, E).
-  __device__ static __forceinline__ void run(C (&v)[E], C* lds, int tl, rsrc_t tw) {
+  // nz = 2 or 4 (wave-uniform) when the first pass is radix 16 and each of
+  // the wave's first-pass groups is zero except v[0] and v[15] (2), or except
+  // v[0], v[1], v[14], v[15] (4): that pass then skips the zero terms, with
+  // the same results; any other value runs the full transform.
+  __device__ static __forceinline__ void run(C (&v)[E], C* lds, int tl, rsrc_t tw, int nz = 0) {
     C w[E];
-    pass<1>(v, w, lds, tl, tw);
+    pass<1>(v, w, lds, tl, tw, nz);
   }
   // offsets of register element i from the thread's own index tl
   static constexpr int in_off(int i) { return (i / R0) * TPR + (i % R0) * (L / R0); }

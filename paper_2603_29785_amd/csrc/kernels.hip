@@ -547,7 +547,18 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
       v[i] = C{val.x * w, val.y * w};
     }
   }
-  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+  // Inputs outside the row's kept offsets [jlo, jhi] are zero; when every
+  // lane of this wave has zeros in first-pass inputs 1..14 (or 2..13) the
+  // first pass skips them (same results, fewer operations).
+  int nz = 0;
+  if constexpr (kWaveRow && F::R0 == 16) {
+    const int jlo = rm.lo - rm.s, jhi = rm.hi - rm.s;
+    const int t0 = __builtin_amdgcn_readfirstlane(tl) & ~63;
+    constexpr int Q = L / 16;   // input i of lane tl sits at slot tl + i Q
+    auto zero = [&](int a, int b) { return t0 + a * Q > jhi && t0 + 63 + b * Q < L + jlo; };
+    nz = zero(1, 14) ? 2 : (zero(2, 13) ? 4 : 0);
+  }
+  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw), nz);
   const int64_t r0 = int64_t(u) * Geo::G;
   const int64_t nrow = total - r0 < Geo::G ? total - r0 : Geo::G;
   const rsrc_t ry = make_rsrc(Y + r0 * L, static_cast<uint32_t>(nrow * L * sizeof(C)));
