@@ -320,3 +320,63 @@ def test_masked_coefficients_inverse(torch_dev):
     keep[:, 100:200] = 0
     xr = gp.inverse(torch.from_numpy(keep).cuda()).cpu().numpy()
     assert rel(xr, op.inverse(keep)) <= 1e-12
+
+
+def random_plans(seed, count):
+    """Seeded random plans over the supported shapes: N = r 2^k (r = 1, 3, 5),
+    bands from near DC to Nyquist, every window family, automatic, odd
+    (chirp-z) and oversized power-of-two N_out; only frames with condition
+    number <= 1e3, where the bars apply."""
+    import paper_2603_29785_amd as qt
+    rng = np.random.default_rng(seed)
+    wins = [("bisquare", o.WIN_BISQUARE, 0.0), ("hann", o.WIN_HANN, 0.0), ("kaiser", o.WIN_KAISER, 5.0),
+            ("tukey", o.WIN_TUKEY, 0.4), ("planck", o.WIN_PLANCK, 0.25)]
+    out = []
+    while len(out) < count:
+        r = int(rng.choice([1, 3, 5]))
+        n = r * 2 ** int(rng.integers(7 if r == 1 else 5, 16 if r == 1 else 13))
+        fs = float(rng.choice([256.0, 1024.0, 4096.0]))
+        nyq = fs / 2
+        fmin = float(rng.uniform(0.005, 0.2)) * nyq
+        fmax = float(rng.choice([nyq, rng.uniform(0.4, 0.95) * nyq]))
+        if fmin < 2 * fs / n:          # at least two bins above DC
+            continue
+        rows = int(rng.integers(3, 97))
+        q = float(rng.uniform(2.0, 24.0))
+        wname, wid, wparam = wins[int(rng.integers(len(wins)))]
+        host = qt.Plan(fs, n, q, fmin, fmax, rows, window=wname, window_param=wparam, host_only=True)
+        kind = int(rng.integers(3))
+        n_out = 0 if kind == 0 else (host.info.max_len if kind == 1 else 2 * host.N_out)
+        if n_out and (n_out > 8192 or n_out < 4):
+            continue
+        info = host.info
+        if not (info.frame_A > 0 and info.frame_B / info.frame_A <= 1e3):
+            continue
+        out.append((fs, n, q, fmin, fmax, rows, wname, wid, wparam, n_out))
+    return out
+
+
+RANDOM = random_plans(2026, 16)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("spec", RANDOM, ids=[f"N{s[1]}_R{s[5]}_{s[6]}_nout{s[9]}" for s in RANDOM])
+def test_random_plans_parity(torch_dev, spec, precision):
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    fs, n, q, fmin, fmax, rows, wname, wid, wparam, n_out = spec
+    print("random plan", spec, precision, flush=True)
+    gp = qt.Plan(fs, n, q, fmin, fmax, rows, window=wname, window_param=wparam, precision=precision, n_out=n_out)
+    op = o.OraclePlan(fs=fs, n=n, q=q, f_min=fmin, f_max=fmax, rows=rows, window=wid, window_param=wparam,
+                      n_out=n_out)
+    assert gp.N_out == op.N_out and gp.R == op.R
+    B = 3
+    x = host_input(np.stack([synthetic.injected_segment(n, fs, synthetic.rng_for(21, i))[0] for i in range(B)]),
+                   precision)
+    Y_ref = op.forward(x)
+    Y = gp.forward(to_dev(torch, x, precision)).cpu().numpy()
+    assert rel_rows(Y, Y_ref).max() <= TOL[precision]
+    Yc = Y_ref.astype(np.complex64).astype(np.complex128) if precision == "fp32" else Y_ref
+    cdt = torch.complex64 if precision == "fp32" else torch.complex128
+    xr = gp.inverse(torch.from_numpy(Yc).to(cdt).cuda()).cpu().numpy()
+    assert rel_rows(xr, op.inverse(Yc)).max() <= TOL[precision]
