@@ -31,7 +31,7 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
           "-munsafe-fp-atomics", "-ffp-contract=on"]
 
 SOURCES = [
-    ("kernels.hip", True),
+    ("libqtam.hip", True),
     ("plan.cpp", False),
 ]
 

@@ -1,21 +1,25 @@
-// QTAM forward / inverse transform kernels for gfx950 (MI355X).
+// libqtam: QTAM forward / inverse transform on gfx950 (MI355X), host side.
+// Plan upload, workspace layout, kernel dispatch and the C ABI of qtam.h; the
+// kernels themselves are in spectrum_kernels.hpp, row_kernels.hpp and
+// ola_kernels.hpp.
 //
 // Forward (Sec. III; App. A):
 //   1. spectrum: the N real samples of a segment, read as N/2 complex pairs
 //      z[m] = x[2m] + i x[2m+1], go through an N/2-point complex FFT
 //      (one LDS pass when N/2 fits a workgroup, else two passes of the
-//      four-step factorisation N/2 = N1 * N2 through the workspace);
-//   2. rows: one fused kernel per (segment, row) rebuilds the real-signal
-//      spectrum X[c] from the packed halves on the fly, multiplies by the
-//      window table, drops each bin at its baseband slot (c - s_k) mod N_out
-//      (roll to baseband, crop, zero pad) and runs the N_out-point inverse
-//      FFT in registers and LDS, storing the envelope row coalesced.
+//      four-step factorisation N/2 = N1 * N2 through the workspace), and the
+//      real-signal twist gives X[0..N/2] (fused into the second pass);
+//   2. rows: one fused kernel per (segment, row) gathers X over the row's
+//      kept support, multiplies by the window, drops each bin at its baseband
+//      slot (c - s_k) mod N_out (roll to baseband, crop, zero pad) and runs
+//      the N_out-point inverse FFT in registers and LDS, storing the envelope
+//      row coalesced.
 // Inverse (Sec. III canonical dual; App. C):
 //   1. rows: N_out-point FFT of each envelope row; the kept slots, weighted
 //      by the dual table sqrt(N/N_out) W M / P / N, go to a packed buffer;
-//   2. overlap-add: each thread sums the covering rows of a bin pair
-//      (b, N/2-b) in fixed row order (no atomics) and applies the real-signal
-//      pre-twist, giving the N/2-point half-size spectrum;
+//   2. overlap-add: each wave sums the covering rows of its bins and their
+//      mirrors N/2 - b in fixed row order (no atomics) and applies the
+//      real-signal pre-twist, giving the N/2-point half-size spectrum;
 //   3. synthesis: N/2-point inverse FFT whose complex output, read as pairs
 //      of reals, is the time series.
 // The adjoints reuse the same kernels with other tables (App. C: the
@@ -31,958 +35,11 @@
 #include <new>
 #include <vector>
 
-#include "fft_engine.hpp"
+#include "ola_kernels.hpp"
 #include "plan.hpp"
 #include "qtam.h"
-
-namespace qtam {
-
-// ---------------------------------------------------------------------------
-// Device-side tables
-// ---------------------------------------------------------------------------
-struct RowMeta {
-  int s, lo, hi, off;   // centre bin, kept bin range, offset in the packed tables
-};
-
-// exp(-2 pi i m / N) for m in [0, N) as fine[m & (F-1)] * coarse[m >> log2 F]
-template <typename C>
-struct Twiddle2 {
-  const C* fine;
-  const C* coarse;
-  int bits;
-  __device__ __forceinline__ C operator()(int64_t m) const {
-    const int64_t lo = m & ((int64_t(1) << bits) - 1);
-    return c_mul(fine[lo], coarse[m >> bits]);
-  }
-};
-
-// ---------------------------------------------------------------------------
-// Launch geometry
-// ---------------------------------------------------------------------------
-template <typename T> constexpr int elems_per_thread() { return sizeof(T) == 4 ? 16 : 8; }
-
-template <typename T, int L>
-struct RowGeom {
-  static constexpr int E = L < elems_per_thread<T>() ? L : elems_per_thread<T>();
-  static constexpr int TPR = L / E;
-  static constexpr int G = TPR >= 256 ? 1 : 256 / TPR;   // transforms per workgroup
-  static constexpr int NT = G * TPR;
-};
-
-// Columns per workgroup of the four-step passes: C * L values fill at most
-// 64 KiB of LDS, at least 4 columns for 32/64-byte contiguous runs.
-template <typename T, int L>
-struct ColGeom {
-  static constexpr int E = L < elems_per_thread<T>() ? L : elems_per_thread<T>();
-  static constexpr int TPR = L / E;
-  static constexpr int CAP = (65536 / (2 * int(sizeof(T)))) / L;
-  static constexpr int CC = CAP >= 16 ? 16 : (CAP >= 4 ? CAP : 4);
-  static constexpr int NT = CC * TPR;
-};
-
-// ---------------------------------------------------------------------------
-// Kernels
-// ---------------------------------------------------------------------------
-
-// Batched contiguous complex FFTs of length L: transform t reads
-// in[t*stride + n] and writes out[t*stride + k]. A chunk holds count
-// transforms; every buffer of it is below 2 GiB.
-template <typename T, int L, int S>
-__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fft_rows(
-    const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
-    int64_t count, int64_t stride, const typename Complex<T>::type* __restrict__ tw) {
-  using C = typename Complex<T>::type;
-  using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, S>;
-  __shared__ C lds[Geo::G * lds_size(L)];
-  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
-  const int64_t tr0 = int64_t(blockIdx.x) * Geo::G;
-  const int64_t nt = count - tr0 < Geo::G ? count - tr0 : Geo::G;   // transforms of this block
-  const uint32_t bytes = static_cast<uint32_t>((nt - 1) * stride + L) * sizeof(C);
-  // lanes of transforms past the end fall outside [0, bytes): loads give 0
-  const rsrc_t rin = make_rsrc(in + tr0 * stride, bytes);
-  const rsrc_t rout = make_rsrc(out + tr0 * stride, bytes);
-  const uint32_t vb = static_cast<uint32_t>(g * stride + tl) * sizeof(C);
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = bload<C>(rin, vb, F::in_off(i) * sizeof(C));
-  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
-  if (g < nt) {
-#pragma unroll
-    for (int i = 0; i < Geo::E; ++i) bstore<C>(rout, v[i], vb, F::out_off(i) * sizeof(C));
-  }
-}
-
-// Four-step, first pass: length-N2 FFTs down the columns n1 of the N1 x N2
-// view (element stride N1), times exp(S 2 pi i n1 k2 / M), written back in
-// place-order. CC adjacent columns per workgroup, column index fastest
-// across threads so every access is a contiguous run of CC values.
-template <typename T, int L, int S>
-__global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_cols(
-    const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
-    int64_t n1_count, int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw,
-    Twiddle2<typename Complex<T>::type> tw2, int tw_mul) {
-  using C = typename Complex<T>::type;
-  using Geo = ColGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, S>;
-  __shared__ C lds[Geo::CC * lds_size(L)];
-  const int t = threadIdx.x, c = t % Geo::CC, tl = t / Geo::CC;
-  const int64_t n1 = int64_t(blockIdx.x) * Geo::CC + c;
-  const int64_t base = int64_t(blockIdx.y) * seg_stride + n1;
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = in[base + n1_count * F::in_index(tl, i)];
-  F::run(v, lds + c * lds_size(L), tl, F::twiddles(tw));
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int64_t k2 = F::out_index(tl, i);
-    // exp(-2 pi i n1 k2 / M), M = N1 N2, from the table of exp(-2 pi i m / (tw_mul M))
-    C w = tw2(tw_mul * n1 * k2);
-    if constexpr (S > 0) w.y = -w.y;
-    out[base + n1_count * k2] = c_mul(v[i], w);
-  }
-}
-
-// Four-step, second pass: length-N1 FFTs along the contiguous rows k2 of the
-// intermediate; CC rows per workgroup are staged through LDS with a linear
-// (coalesced) load, results go to Z[k2 + N2 k1] in runs of CC values.
-template <typename T, int L, int S>
-__global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_rows_t(
-    const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
-    int64_t n2_count, int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw) {
-  using C = typename Complex<T>::type;
-  using Geo = ColGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, S>;
-  __shared__ C lds[Geo::CC * lds_size(L)];
-  const int t = threadIdx.x;
-  const int64_t k2_0 = int64_t(blockIdx.x) * Geo::CC;
-  const C* src = in + int64_t(blockIdx.y) * seg_stride + k2_0 * L;
-  for (int i = t; i < Geo::CC * L; i += Geo::NT) lds[(i / L) * lds_size(L) + lds_pad(i % L)] = src[i];
-  __syncthreads();
-  const int c = t % Geo::CC, tl = t / Geo::CC;
-  C* reg = lds + c * lds_size(L);
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = reg[lds_pad(F::in_index(tl, i))];
-  __syncthreads();
-  F::run(v, reg, tl, F::twiddles(tw));
-  C* dst = out + int64_t(blockIdx.y) * seg_stride + k2_0 + c;
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) dst[n2_count * F::out_index(tl, i)] = v[i];
-}
-
-// Four-step second pass fused with the real-signal twist (k_twist below): the
-// output of row k2 at k1 (bin m = k2 + N2 k1 of Z) meets its mirror
-// N/2 - m in row N2 - k2 at N1 - 1 - k1 (row 0: itself at N1 - k1 mod N1), so
-// a workgroup takes mirrored row pairs: H = CC/2 rows j H + c and their
-// mirrors N2 - j H - c (workgroup 0: rows 0 .. H-1, N2/2 and N2-H+1 .. N2-1,
-// rows 0 and N2/2 being their own mirrors). After the row transforms the
-// values go through LDS to the thread that twists each bin.
-template <typename T, int L>
-__global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_spec_rows_twist(
-    const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out, int64_t n2,
-    int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw, Twiddle2<typename Complex<T>::type> tw2) {
-  using C = typename Complex<T>::type;
-  using Geo = ColGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, -1>;
-  constexpr int CC = Geo::CC, H = CC / 2;
-  static_assert(CC % 2 == 0, "paired rows");
-  __shared__ C lds[CC * lds_size(L)];
-  const int t = threadIdx.x;
-  const int64_t j = blockIdx.x;
-  auto row_of = [&](int c) -> int64_t {
-    if (j == 0) return c < H ? c : (c == H ? n2 / 2 : n2 - (c - H));
-    return c < H ? j * H + c : n2 - (j * H + (c - H));
-  };
-  const C* src = in + int64_t(blockIdx.y) * seg_stride;
-  for (int i = t; i < CC * L; i += Geo::NT) {
-    const int c = i / L;
-    lds[c * lds_size(L) + lds_pad(i % L)] = src[row_of(c) * L + (i % L)];
-  }
-  __syncthreads();
-  const int c = t % CC, tl = t / CC;
-  C* reg = lds + c * lds_size(L);
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = reg[lds_pad(F::in_index(tl, i))];
-  __syncthreads();
-  F::run(v, reg, tl, F::twiddles(tw));
-  // every transform's output into its own LDS column, then the twist
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) reg[lds_pad(F::out_index(tl, i))] = v[i];
-  __syncthreads();
-  const int64_t r = row_of(c);
-  const int pc = (j == 0 && (c == 0 || c == H)) ? c : (c < H ? c + H : c - H);
-  const C* preg = lds + pc * lds_size(L);
-  C* dst = out + int64_t(blockIdx.y) * seg_stride;
-  const T hh = T(0.5);
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int k1 = F::out_index(tl, i);
-    const int64_t m = r + n2 * k1;
-    const C zp = v[i];
-    if (m == 0) {   // X[0] and X[N/2] share slot 0
-      dst[0] = C{zp.x + zp.y, zp.x - zp.y};
-      continue;
-    }
-    const int k1m = r == 0 ? (L - k1) & (L - 1) : L - 1 - k1;
-    const C zq = preg[lds_pad(k1m)];
-    const C w = tw2(m);                          // e^{-2 pi i m / N}
-    const C a = c_add(zp, c_conj(zq)), b = c_sub(zp, c_conj(zq));
-    const C xp = c_add(a, c_mul_si<-1>(c_mul(w, b)));
-    dst[m] = C{xp.x * hh, xp.y * hh};
-  }
-}
-
-// Real-signal spectrum from the N/2-point FFT Z of the even/odd pairs of a
-// segment, in place: for c in [0, N/2]
-//   X[c] = (Z[c] + Z*[N/2-c])/2 - (i/2) e^{-2 pi i c/N} (Z[c] - Z*[N/2-c])
-// (indices of Z mod N/2). Thread p owns the pair (p, N/2-p); the two real
-// values X[0] and X[N/2] share slot 0 as (X[0], X[N/2]).
-template <typename T>
-__global__ __launch_bounds__(256) void k_twist(typename Complex<T>::type* __restrict__ Z, int64_t half,
-                                              Twiddle2<typename Complex<T>::type> tw2) {
-  using C = typename Complex<T>::type;
-  const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (p > half / 2) return;
-  C* z = Z + int64_t(blockIdx.y) * half;
-  const T h = T(0.5);
-  if (p == 0) {
-    const C z0 = z[0];
-    z[0] = C{z0.x + z0.y, z0.x - z0.y};
-    return;
-  }
-  const int64_t q = half - p;
-  const C zp = z[p], zq = z[q];
-  const C w = tw2(p);                           // e^{-2 pi i p/N}; at q it is -conj(w)
-  const C a = c_add(zp, c_conj(zq)), b = c_sub(zp, c_conj(zq));
-  const C xp = c_add(a, c_mul_si<-1>(c_mul(w, b)));
-  const C a2 = c_add(zq, c_conj(zp)), b2 = c_sub(zq, c_conj(zp));
-  const C xq = c_sub(a2, c_mul_si<-1>(c_mul(c_conj(w), b2)));
-  z[p] = C{xp.x * h, xp.y * h};
-  if (q != p) z[q] = C{xq.x * h, xq.y * h};
-}
-
-// Segment lengths with N/2 = r * M2, r in {3, 5}, M2 a power of two: the
-// half-size transform splits into r interleaved length-M2 transforms
-// (decimation by r) and one radix-r combination.
-//   forward:  Zp[n1][n2] = z[n1 + r n2];  F_n1 = DFT_M2(Zp[n1]);
-//             Z[k2 + M2 k1] = sum_n1 e^{-2 pi i n1 k1 / r} e^{-2 pi i n1 k2 / (N/2)} F_n1[k2]
-//   inverse:  A_n1[k2] = e^{+2 pi i n1 k2 / (N/2)} sum_k1 Z[k2 + M2 k1] e^{+2 pi i n1 k1 / r};
-//             z[n1 + r n2] = IDFT_M2(A_n1)[n2]
-// k_permute moves a segment between the natural order z[n] and the decimated
-// rows Zp[n1][n2] (TO_ROWS) or back; k_radix does the combination.
-template <typename T, bool TO_ROWS>
-__global__ __launch_bounds__(256) void k_permute(const typename Complex<T>::type* __restrict__ in,
-                                                 typename Complex<T>::type* __restrict__ out, int r, int64_t m2) {
-  const int64_t half = r * m2;
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;   // index in the decimated rows
-  if (i >= half) return;
-  const int64_t n1 = i / m2, n2 = i - n1 * m2;
-  const int64_t n = n1 + r * n2;
-  const int64_t base = int64_t(blockIdx.y) * half;
-  if constexpr (TO_ROWS) out[base + i] = in[base + n];
-  else out[base + n] = in[base + i];
-}
-
-// cos / sin of 2 pi k / R for R = 3, 5
-template <typename T, int R>
-__device__ __forceinline__ typename Complex<T>::type root_r(int k) {
-  using C = typename Complex<T>::type;
-  if constexpr (R == 3) {
-    constexpr T c1 = static_cast<T>(-0.5), s1 = static_cast<T>(0.86602540378443864676);
-    return k == 0 ? C{1, 0} : (k == 1 ? C{c1, s1} : C{c1, -s1});
-  } else {
-    constexpr T c1 = static_cast<T>(0.30901699437494742410), s1 = static_cast<T>(0.95105651629515357212);
-    constexpr T c2 = static_cast<T>(-0.80901699437494742410), s2 = static_cast<T>(0.58778525229247312917);
-    return k == 0 ? C{1, 0} : k == 1 ? C{c1, s1} : k == 2 ? C{c2, s2} : k == 3 ? C{c2, -s2} : C{c1, -s1};
-  }
-}
-
-template <typename T, int R, int S>
-__global__ __launch_bounds__(256) void k_radix(const typename Complex<T>::type* __restrict__ in,
-                                               typename Complex<T>::type* __restrict__ out, int64_t m2,
-                                               Twiddle2<typename Complex<T>::type> tw2) {
-  using C = typename Complex<T>::type;
-  const int64_t k2 = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (k2 >= m2) return;
-  const int64_t base = int64_t(blockIdx.y) * R * m2;
-  C a[R], b[R];
-  if constexpr (S < 0) {
-    // F_n1[k2] times e^{-2 pi i n1 k2 / (N/2)} = tw2(2 n1 k2), then the radix-R DFT over n1
-#pragma unroll
-    for (int n1 = 0; n1 < R; ++n1) {
-      const C f = in[base + n1 * m2 + k2];
-      a[n1] = n1 == 0 ? f : c_mul(f, tw2(2 * n1 * k2));
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) {
-      C acc = a[0];
-#pragma unroll
-      for (int n1 = 1; n1 < R; ++n1) acc = c_add(acc, c_mul(a[n1], c_conj(root_r<T, R>((n1 * k1) % R))));
-      b[k1] = acc;
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) out[base + k2 + m2 * k1] = b[k1];
-  } else {
-#pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) a[k1] = in[base + k2 + m2 * k1];
-#pragma unroll
-    for (int n1 = 0; n1 < R; ++n1) {
-      C acc = a[0];
-#pragma unroll
-      for (int k1 = 1; k1 < R; ++k1) acc = c_add(acc, c_mul(a[k1], root_r<T, R>((n1 * k1) % R)));
-      b[n1] = n1 == 0 ? acc : c_mul(acc, c_conj(tw2(2 * n1 * k2)));
-    }
-#pragma unroll
-    for (int n1 = 0; n1 < R; ++n1) out[base + n1 * m2 + k2] = b[n1];
-  }
-}
-
-// Dense tiles: row k of segment s as an N-point spectrum holding its packed
-// kept entries at their bins lo..hi and zeros elsewhere (the inverse FFT of
-// that row is the dense tile). One thread per output bin, rows in grid.y.
-template <typename T>
-__global__ __launch_bounds__(256) void k_place(const typename Complex<T>::type* __restrict__ Sbuf,
-                                               typename Complex<T>::type* __restrict__ D, const RowMeta* __restrict__ rows,
-                                               int R, int64_t n, int64_t sum_len) {
-  using C = typename Complex<T>::type;
-  const int64_t b = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (b >= n) return;
-  const int64_t gr = blockIdx.y;
-  const int64_t seg = gr / R;
-  const RowMeta rm = rows[gr - seg * R];
-  const bool in = b >= rm.lo && b <= rm.hi;
-  D[gr * n + b] = in ? Sbuf[seg * sum_len + rm.off + (b - rm.lo)] : C{0, 0};
-}
-
-// Single-tile recovery: row `row` of each segment, its N_out-point forward
-// transform, every slot whose bin c = s + j lies in 0..N/2 times the tile
-// table (sqrt(N/N_out) / W / N) into Sx[seg][c]. One segment per row group.
-template <typename T, int L>
-__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_tile_rows(
-    const typename Complex<T>::type* __restrict__ Y, typename Complex<T>::type* __restrict__ Sx,
-    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int row, int segs, int half,
-    const typename Complex<T>::type* __restrict__ tw) {
-  using C = typename Complex<T>::type;
-  using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, -1, TW_MIXED>;
-  __shared__ C lds[Geo::G * lds_size(L)];
-  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
-  const int seg = static_cast<int>(blockIdx.x) * Geo::G + g;
-  const bool ok = seg < segs;
-  const rsrc_t ry = make_rsrc(Y + (int64_t(ok ? seg : 0) * R + row) * L, ok ? static_cast<uint32_t>(L * sizeof(C)) : 0u);
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = bload<C>(ry, static_cast<uint32_t>(tl + F::in_off(i)) * sizeof(C));
-  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
-  if (!ok) return;
-  const RowMeta rm = rows[row];
-  C* dst = Sx + int64_t(seg) * (half + 1);
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int off = F::out_off(i);
-    const int c = rm.s + tl + (off < L / 2 ? off : off - L);
-    if (c >= rm.lo && c <= rm.hi) {
-      const T w = tab[rm.off + c - rm.lo];
-      dst[c] = C{v[i].x * w, v[i].y * w};
-    }
-  }
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
-// XCD i mod 8) and roughly in index order. Renumbering them so that XCD x
-// takes the x-th eighth of the units makes the workgroups resident on one XCD
-// at a time work on neighbouring rows, whose spectrum that XCD's L2 holds.
-__device__ __forceinline__ int xcd_major_block(int nblocks) {
-  const int b = blockIdx.x;
-  if (nblocks & 7) return b;
-  return (b & 7) * (nblocks >> 3) + (b >> 3);
-}
-
-// Fused forward rows: the windowed spectrum bins of a row are dropped at
-// their baseband slots (c - s_k) mod N_out (roll to baseband, crop, zero pad),
-// the N_out-point inverse FFT runs in registers and LDS, and the envelope row
-// is stored. One unit of G consecutive rows per workgroup.
-// Cache policy of the envelope stores: Y is written once and not read again
-// by the forward, so streaming it past the L2 keeps the spectrum and the plan
-// tables, which every row re-reads, resident there (measured: the forward
-// rows kernel of the batched workload drops from 0.70 to 0.50 ms). Loads of
-// Y by the inverse keep the default policy (streaming them measured no gain
-// and slowed the overlap-add that follows).
-constexpr int kYStore = kCacheNT;
-constexpr int kYLoad = kCacheDefault;
-// The packed kept slots are read once, by the overlap-add after the whole
-// inverse-rows launch: streamed as well (measured 1-3% on both kernels).
-constexpr int kSStore = kCacheNT;
-
-// Hides a value's derivation from the optimiser (an empty asm that keeps it
-// in a VGPR), so per-element offsets stay one add from a precomputed base
-// instead of being refolded into an add and a shift per resource.
-__device__ __forceinline__ void opaque(unsigned& v) { asm volatile("" : "+v"(v)); }
-
-// Row statistics (sum and max of |Y|^2 over the row) of the E values each of
-// a row's TPR threads holds. Lanes of one row inside a wave combine by an xor
-// butterfly (every lane ends with the same bits); rows spanning several waves
-// then add the per-wave results in wave order through `part` (LDS the
-// transform no longer reads, NT/64 elements). Every thread of the block must
-// call it.
-template <typename T, int E, int TPR, int NT>
-__device__ __forceinline__ void row_stats(const typename Complex<T>::type (&v)[E], int tl, bool ok,
-                                          typename Complex<T>::type* __restrict__ dst,
-                                          typename Complex<T>::type* __restrict__ part) {
-  using C = typename Complex<T>::type;
-  constexpr int W = TPR < 64 ? TPR : 64;     // lanes of a row within one wave
-  constexpr int WPR = TPR > 64 ? TPR / 64 : 1;
-  T e = 0, m = 0;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const T a = v[i].x * v[i].x + v[i].y * v[i].y;
-    e += a;
-    m = fmax(m, a);
-  }
-#pragma unroll
-  for (int o = 1; o < W; o <<= 1) {
-    e += __shfl_xor(e, o, W);
-    m = fmax(m, __shfl_xor(m, o, W));
-  }
-  if constexpr (WPR == 1) {
-    if (ok && tl == 0) *dst = C{e, m};
-  } else {
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = C{e, m};
-    __syncthreads();
-    if (ok && tl == 0) {
-      const C* pr = part + (threadIdx.x >> 6);
-      C r = pr[0];
-#pragma unroll
-      for (int w = 1; w < WPR; ++w) {
-        r.x += pr[w].x;
-        r.y = fmax(r.y, pr[w].y);
-      }
-      *dst = r;
-    }
-  }
-}
-
-// When a wave holds one row (TPR >= 64) and the row touches neither DC nor
-// Nyquist, buffer resources scoped to the row's kept support do the cropping:
-// slots outside it fall outside the resources and read 0, with no test.
-// Otherwise each slot is tested; ANALYTIC then computes the bisquare weight
-// scale_k (1 - (j/h_k)^2)^2 instead of reading the table.
-template <typename T, int L, bool ANALYTIC, bool STATS>
-__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
-    const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ Y,
-    const RowMeta* __restrict__ rows, const typename Complex<T>::type* __restrict__ roww,
-    const T* __restrict__ tab, int R, int total, int half, int sum_len, int64_t spec_elems,
-    const typename Complex<T>::type* __restrict__ tw, int nblocks, typename Complex<T>::type* __restrict__ stats) {
-  using C = typename Complex<T>::type;
-  using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, +1, TW_MIXED>;
-  constexpr bool kWaveRow = Geo::TPR >= 64;   // every lane of a wave is on the same row
-  __shared__ C lds[Geo::G * lds_size(L)];
-  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
-  const int u = xcd_major_block(nblocks);
-  int gr = u * Geo::G + g;
-  if constexpr (kWaveRow) gr = __builtin_amdgcn_readfirstlane(gr);
-  const bool ok = gr < total;
-  const int seg = ok ? gr / R : 0;
-  const int row = ok ? gr - seg * R : 0;
-  const RowMeta rm = rows[row];
-  C v[Geo::E];
-  if (kWaveRow && rm.lo > 0 && rm.hi < half) {
-    const int len = rm.hi - rm.lo + 1;
-    const rsrc_t rz = make_rsrc(spec + int64_t(seg) * half + rm.lo, ok ? static_cast<uint32_t>(len * sizeof(C)) : 0u);
-    const rsrc_t rt = make_rsrc(tab + rm.off, ok ? static_cast<uint32_t>(len * sizeof(T)) : 0u);
-    const int db = rm.s - rm.lo + tl;   // kept-bin index d = c - lo of the slot with offset 0
-    // byte offsets of d in both resources, advanced by constants (negative d
-    // wraps beyond the resource and reads 0)
-    unsigned bx = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(C));
-    unsigned bw = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(T));
-    opaque(bx);
-    opaque(bw);
-#pragma unroll
-    for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::in_off(i);
-      const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
-      const C x = bload<C>(rz, bx + j * static_cast<unsigned>(sizeof(C)));
-      const T w = bload<T>(rt, bw + j * static_cast<unsigned>(sizeof(T)));
-      v[i] = C{x.x * w, x.y * w};
-    }
-  } else {
-    const rsrc_t rz = make_rsrc(spec, static_cast<uint32_t>(spec_elems * sizeof(C)));
-    const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
-
-    const unsigned zb = static_cast<unsigned>(seg) * static_cast<unsigned>(half);
-    const int cb = rm.s + tl;
-    // X[c] of the slots in the kept support; other slots get an offset beyond
-    // the buffer and read 0 without touching memory
-#pragma unroll
-    for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::in_off(i);
-      const int c = cb + (off < L / 2 ? off : off - L);   // slot tl + off holds offset j = slot or slot - L
-      const bool in = ok && c >= rm.lo && c <= rm.hi;
-      const unsigned vo = in ? (zb + static_cast<unsigned>(c == half ? 0 : c)) * static_cast<unsigned>(sizeof(C))
-                             : 0xFFFFFFFFu;
-      v[i] = bload<C>(rz, vo);
-    }
-    C sw{0, 0};
-    if constexpr (ANALYTIC) sw = roww[row];   // (scale_k, 1/h_k)
-#pragma unroll
-    for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::in_off(i);
-      const int j = tl + (off < L / 2 ? off : off - L);
-      const int c = rm.s + j;
-      C val = v[i];
-      if (c == 0) val.y = 0;               // slot 0 of the spectrum holds (X[0], X[N/2])
-      if (c == half) val = C{val.y, 0};
-      T w;
-      if constexpr (ANALYTIC) {
-        const T x = static_cast<T>(j) * sw.y;
-        const T b = (T(1) - x) * (T(1) + x);
-        w = sw.x * b * b;
-      } else {
-        const bool in = ok && c >= rm.lo && c <= rm.hi;
-        w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off - rm.lo + c : 0) * sizeof(T));
-      }
-      v[i] = C{val.x * w, val.y * w};
-    }
-  }
-  // Inputs outside the row's kept offsets [jlo, jhi] are zero; when every
-  // lane of this wave has zeros in first-pass inputs 1..14 (or 2..13) the
-  // first pass skips them (same results, fewer operations).
-  int nz = 0;
-  if constexpr (kWaveRow && F::R0 == 16) {
-    const int jlo = rm.lo - rm.s, jhi = rm.hi - rm.s;
-    const int t0 = __builtin_amdgcn_readfirstlane(tl) & ~63;
-    constexpr int Q = L / 16;   // input i of lane tl sits at slot tl + i Q
-    auto zero = [&](int a, int b) { return t0 + a * Q > jhi && t0 + 63 + b * Q < L + jlo; };
-    nz = zero(1, 14) ? 2 : (zero(2, 13) ? 4 : 0);
-  }
-  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw), nz);
-  const int64_t r0 = int64_t(u) * Geo::G;
-  const int64_t nrow = total - r0 < Geo::G ? total - r0 : Geo::G;
-  const rsrc_t ry = make_rsrc(Y + r0 * L, static_cast<uint32_t>(nrow * L * sizeof(C)));
-  const uint32_t vb = static_cast<uint32_t>(g * L + tl) * sizeof(C);
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) bstore<C, kYStore>(ry, v[i], vb, F::out_off(i) * sizeof(C));
-  if constexpr (STATS) row_stats<T, Geo::E, Geo::TPR, Geo::NT>(v, tl, ok, stats + gr, lds);
-}
-
-// Inverse rows: N_out-point FFT of each envelope row; the kept slots times the
-// table go to the packed per-segment buffer Sbuf[seg * sum_len + off + c - lo].
-// With one row per wave, resources scoped to the row's packed entries drop
-// the other slots' stores without a test.
-template <typename T, int L>
-__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
-    const typename Complex<T>::type* __restrict__ Y, typename Complex<T>::type* __restrict__ Sbuf,
-    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int total, int sum_len, int segs,
-    const typename Complex<T>::type* __restrict__ tw) {
-  using C = typename Complex<T>::type;
-  using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, -1, TW_MIXED>;
-  constexpr bool kWaveRow = Geo::TPR >= 64;
-  __shared__ C lds[Geo::G * lds_size(L)];
-  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
-  const int64_t r0 = int64_t(blockIdx.x) * Geo::G;
-  const int64_t nrow = total - r0 < Geo::G ? total - r0 : Geo::G;
-  const rsrc_t ry = make_rsrc(Y + r0 * L, static_cast<uint32_t>(nrow * L * sizeof(C)));
-  const uint32_t vb = static_cast<uint32_t>(g * L + tl) * sizeof(C);
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = bload<C, kYLoad>(ry, vb, F::in_off(i) * sizeof(C));
-  if constexpr (kWaveRow) {
-    // the row's weights are requested before the transform, so their latency
-    // hides behind it; rows past the end get empty resources
-    const int gr = __builtin_amdgcn_readfirstlane(static_cast<int>(r0) + g);
-    const bool ok = gr < total;
-    const int seg = ok ? gr / R : 0;
-    const RowMeta rm = rows[ok ? gr - seg * R : 0];
-    const int len = ok ? rm.hi - rm.lo + 1 : 0;
-    const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
-    const rsrc_t rs = make_rsrc(Sbuf + int64_t(seg) * sum_len + rm.off, static_cast<uint32_t>(len * sizeof(C)));
-    const rsrc_t rt = make_rsrc(tab + rm.off, static_cast<uint32_t>(len * sizeof(T)));
-    unsigned bs = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(C));
-    unsigned bw = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(T));
-    opaque(bs);
-    opaque(bw);
-    T w[Geo::E];
-#pragma unroll
-    for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::out_off(i);
-      const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
-      w[i] = bload<T>(rt, bw + j * static_cast<unsigned>(sizeof(T)));
-    }
-    F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
-#pragma unroll
-    for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::out_off(i);
-      const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
-      bstore<C, kSStore>(rs, C{v[i].x * w[i], v[i].y * w[i]}, bs + j * static_cast<unsigned>(sizeof(C)));
-    }
-  } else {
-    F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
-    const int gr = static_cast<int>(r0) + g;
-    if (gr >= total) return;
-    const int seg = gr / R;
-    const RowMeta rm = rows[gr - seg * R];
-    const int len = rm.hi - rm.lo + 1;
-    const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
-    const rsrc_t rs = make_rsrc(Sbuf, static_cast<uint32_t>(int64_t(segs) * sum_len * sizeof(C)));
-    const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
-    const unsigned sb = static_cast<unsigned>(seg) * static_cast<unsigned>(sum_len) + static_cast<unsigned>(rm.off);
-#pragma unroll
-    for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::out_off(i);
-      const int d = db + (off < L / 2 ? off : off - L);
-      if (static_cast<unsigned>(d) < static_cast<unsigned>(len)) {
-        const T w = bload<T>(rt, (rm.off + d) * sizeof(T));
-        bstore<C, kSStore>(rs, C{v[i].x * w, v[i].y * w}, (sb + d) * sizeof(C));
-      }
-    }
-  }
-}
-
-// Envelope lengths M = N_out that are not powers of two (the paper's minimal
-// N_out, say): each row's length-M DFT by Bluestein's chirp-z identity,
-//   sum_u g[u] e^{S 2 pi i u m / M} = a[m] sum_u (g[u] a[u]) b[m - u],
-//   a[v] = e^{S pi i v^2 / M}, b[v] = conj(a[v]),
-// the convolution as a cyclic one of power-of-two length L >= 2M - 1: a
-// forward FFT, a product with Bhat = FFT_L(b wrapped) / L, an inverse FFT.
-// Tables (FP64-built): chirp a[0..M) and Bhat[0..L) of the transform's sign.
-template <typename T, int L, typename C, int E>
-__device__ __forceinline__ void chirp_convolve(C (&v)[E], C* lds, int tl, const C* __restrict__ bhat,
-                                               const C* __restrict__ tw) {
-  using Geo = RowGeom<T, L>;
-  static_assert(Geo::E == E, "row geometry");
-  using F = BlockFft<T, L, Geo::E, -1, TW_POW>;
-  using Fi = BlockFft<T, L, Geo::E, +1, TW_POW>;
-  F::run(v, lds, tl, F::twiddles(tw));
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = c_mul(v[i], bhat[tl + F::out_off(i)]);
-  // back to the input order of the second transform
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) lds[lds_pad(tl + F::out_off(i))] = v[i];
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = lds[lds_pad(tl + Fi::in_off(i))];
-  __syncthreads();
-  Fi::run(v, lds, tl, Fi::twiddles(tw));
-}
-
-// Forward rows, M not a power of two: gather the kept bins of each row at
-// their slots (c - s) mod M times the forward table and the chirp, then
-// Bluestein (sign +) and the output chirp; outputs m < M are stored.
-template <typename T, int L>
-__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows_bs(
-    const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ Y,
-    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int total, int half, int sum_len,
-    int64_t spec_elems, int M, const typename Complex<T>::type* __restrict__ chirp,
-    const typename Complex<T>::type* __restrict__ bhat, const typename Complex<T>::type* __restrict__ tw) {
-  using C = typename Complex<T>::type;
-  using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, -1, TW_POW>;
-  using Fi = BlockFft<T, L, Geo::E, +1, TW_POW>;
-  __shared__ C lds[Geo::G * lds_size(L)];
-  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
-  const int gr = static_cast<int>(blockIdx.x) * Geo::G + g;
-  const bool ok = gr < total;
-  const int seg = ok ? gr / R : 0;
-  const RowMeta rm = rows[ok ? gr - seg * R : 0];
-  const rsrc_t rz = make_rsrc(spec, static_cast<uint32_t>(spec_elems * sizeof(C)));
-  const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
-  const unsigned zb = static_cast<unsigned>(seg) * static_cast<unsigned>(half);
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int u = tl + F::in_off(i);                 // Bluestein slot; < M holds data
-    const int j = u <= M / 2 ? u : u - M;            // offset from the centre bin
-    const int c = rm.s + j;
-    const bool in = ok && u < M && c >= rm.lo && c <= rm.hi;
-    const unsigned vo = in ? (zb + static_cast<unsigned>(c == half ? 0 : c)) * static_cast<unsigned>(sizeof(C))
-                           : 0xFFFFFFFFu;
-    C x = bload<C>(rz, vo);
-    if (c == 0) x.y = 0;
-    if (c == half) x = C{x.y, 0};
-    const T w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off - rm.lo + c : 0) * sizeof(T));
-    const C a = chirp[u < M ? u : 0];   // x is 0 outside the support
-    v[i] = c_mul(C{x.x * w, x.y * w}, a);
-  }
-  chirp_convolve<T, L>(v, lds + g * lds_size(L), tl, bhat, tw);
-  if (!ok) return;
-  C* yrow = Y + int64_t(gr) * M;
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int m = tl + Fi::out_off(i);
-    if (m < M) yrow[m] = c_mul(v[i], chirp[m]);
-  }
-}
-
-// Inverse rows, M not a power of two: Bluestein (sign -) over each envelope
-// row, then the kept slots times the table into the packed buffer.
-template <typename T, int L>
-__global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows_bs(
-    const typename Complex<T>::type* __restrict__ Y, typename Complex<T>::type* __restrict__ Sbuf,
-    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int total, int sum_len, int M,
-    const typename Complex<T>::type* __restrict__ chirp, const typename Complex<T>::type* __restrict__ bhat,
-    const typename Complex<T>::type* __restrict__ tw) {
-  using C = typename Complex<T>::type;
-  using Geo = RowGeom<T, L>;
-  using F = BlockFft<T, L, Geo::E, -1, TW_POW>;
-  using Fi = BlockFft<T, L, Geo::E, +1, TW_POW>;
-  __shared__ C lds[Geo::G * lds_size(L)];
-  const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
-  const int gr = static_cast<int>(blockIdx.x) * Geo::G + g;
-  const bool ok = gr < total;
-  const C* yrow = Y + int64_t(ok ? gr : 0) * M;
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int u = tl + F::in_off(i);
-    const bool in = ok && u < M;
-    const int uc = in ? u : 0;
-    const C z = c_mul(yrow[uc], c_conj(chirp[uc]));
-    v[i] = in ? z : C{0, 0};
-  }
-  chirp_convolve<T, L>(v, lds + g * lds_size(L), tl, bhat, tw);
-  if (!ok) return;
-  const int seg = gr / R;
-  const RowMeta rm = rows[gr - seg * R];
-  C* srow = Sbuf + int64_t(seg) * sum_len + rm.off;
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int u = tl + Fi::out_off(i);
-    if (u >= M) continue;
-    const int j = u <= M / 2 ? u : u - M;
-    const int c = rm.s + j;
-    if (c < rm.lo || c > rm.hi) continue;
-    const C z = c_mul(v[i], c_conj(chirp[u]));
-    const T w = tab[rm.off + c - rm.lo];
-    srow[c - rm.lo] = C{z.x * w, z.y * w};
-  }
-}
-
-// Rows longer than one workgroup's LDS transform (four-step over the
-// workspace, N_out = L1 * L2, slot u = n1 + L1 n2, output m = k2 + L2 k1).
-// Forward, first pass: for every row, column n1 gathers its L2 slots from the
-// spectrum (windowed, zero outside the kept support), runs the length-L2
-// inverse FFT, multiplies by exp(+2 pi i n1 k2 / N_out) and stores A[n1 + L1 k2]
-// of the row. The second pass is k_fft_rows_t over the rows (lengths L1).
-template <typename T, int L2>
-__global__ __launch_bounds__((ColGeom<T, L2>::NT)) void k_fwd_rows_cols(
-    const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ A,
-    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int half, int64_t n_out, int64_t l1,
-    const typename Complex<T>::type* __restrict__ tw, Twiddle2<typename Complex<T>::type> tw2) {
-  using C = typename Complex<T>::type;
-  using Geo = ColGeom<T, L2>;
-  using F = BlockFft<T, L2, Geo::E, +1>;
-  __shared__ C lds[Geo::CC * lds_size(L2)];
-  const int t = threadIdx.x, cc = t % Geo::CC, tl = t / Geo::CC;
-  const int64_t n1 = int64_t(blockIdx.x) * Geo::CC + cc;
-  const int64_t gr = blockIdx.y;               // row of the chunk
-  const int64_t seg = gr / R;
-  const RowMeta rm = rows[int(gr - seg * R)];
-  const C* Z = spec + seg * half;
-  const int64_t hn = n_out / 2;
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int64_t u = n1 + l1 * F::in_index(tl, i);
-    const int64_t c = rm.s + (u < hn ? u : u - n_out);
-    C val{0, 0};
-    if (c >= rm.lo && c <= rm.hi) {
-      val = Z[c == half ? 0 : c];
-      if (c == 0) val.y = 0;                  // slot 0 holds (X[0], X[N/2])
-      if (c == half) val = C{val.y, 0};
-      const T w = tab[rm.off + (c - rm.lo)];
-      val = C{val.x * w, val.y * w};
-    }
-    v[i] = val;
-  }
-  F::run(v, lds + cc * lds_size(L2), tl, F::twiddles(tw));
-  C* dst = A + gr * n_out + n1;
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int64_t k2 = F::out_index(tl, i);
-    C w = tw2(n1 * k2);
-    w.y = -w.y;                               // exp(+2 pi i n1 k2 / N_out)
-    dst[l1 * k2] = c_mul(v[i], w);
-  }
-}
-
-// Inverse, second pass over long rows: length-L1 FFTs along the rows k2 of
-// the intermediate (CC rows per workgroup, staged through LDS), then the kept
-// output slots m = k2 + L2 k1 times the table go to the packed buffer.
-template <typename T, int L1>
-__global__ __launch_bounds__((ColGeom<T, L1>::NT)) void k_inv_rows_rowst(
-    const typename Complex<T>::type* __restrict__ A, typename Complex<T>::type* __restrict__ Sbuf,
-    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int64_t sum_len, int64_t n_out,
-    int64_t l2, const typename Complex<T>::type* __restrict__ tw) {
-  using C = typename Complex<T>::type;
-  using Geo = ColGeom<T, L1>;
-  using F = BlockFft<T, L1, Geo::E, -1>;
-  __shared__ C lds[Geo::CC * lds_size(L1)];
-  const int t = threadIdx.x;
-  const int64_t gr = blockIdx.y;
-  const int64_t k2_0 = int64_t(blockIdx.x) * Geo::CC;
-  const C* src = A + gr * n_out + k2_0 * L1;
-  for (int i = t; i < Geo::CC * L1; i += Geo::NT) lds[(i / L1) * lds_size(L1) + lds_pad(i % L1)] = src[i];
-  __syncthreads();
-  const int cc = t % Geo::CC, tl = t / Geo::CC;
-  C* reg = lds + cc * lds_size(L1);
-  C v[Geo::E];
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) v[i] = reg[lds_pad(F::in_index(tl, i))];
-  __syncthreads();
-  F::run(v, reg, tl, F::twiddles(tw));
-  const int64_t seg = gr / R;
-  const RowMeta rm = rows[int(gr - seg * R)];
-  C* dst = Sbuf + seg * sum_len + rm.off - rm.lo;
-  const T* tb = tab + rm.off - rm.lo;
-  const int64_t hn = n_out / 2;
-#pragma unroll
-  for (int i = 0; i < Geo::E; ++i) {
-    const int64_t m = k2_0 + cc + l2 * F::out_index(tl, i);
-    const int64_t c = rm.s + (m < hn ? m : m - n_out);
-    if (c >= rm.lo && c <= rm.hi) {
-      const T w = tb[c];
-      dst[c] = C{v[i].x * w, v[i].y * w};
-    }
-  }
-}
-
-// Overlap-add. Each wave owns 64 consecutive bins p <= N/4 and their mirrors
-// q = N/2 - p. For each side it walks the rows whose kept support meets its
-// bins (a host list per wave, ascending row order, so every bin sums its
-// terms in ascending row order, with no atomics): lanes inside a row's support
-// add that row's packed entry, consecutive lanes reading consecutive entries;
-// lanes outside get an offset beyond the buffer and read 0. Then the
-// real-signal pre-twist turns the one-sided spectrum at p and N/2-p into the
-// half-size spectrum the synthesis FFT consumes.
-struct OlaRow {
-  int lo, span, base, pad;   // kept bins [lo, lo + span], packed entry of bin c at base + c
-};
-
-template <typename C>
-__device__ __forceinline__ C ola_side(rsrc_t rs, const OlaRow* __restrict__ list, int a, int b, int c) {
-  C acc{0, 0};
-#pragma unroll 4
-  for (int i = a; i < b; ++i) {
-    const OlaRow r = list[i];
-    const bool in = static_cast<unsigned>(c - r.lo) <= static_cast<unsigned>(r.span);
-    const unsigned vo = in ? static_cast<unsigned>(r.base + c) * static_cast<unsigned>(sizeof(C)) : 0xFFFFFFFFu;
-    acc = c_add(acc, bload<C>(rs, vo));
-  }
-  return acc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_ola(
-    const typename Complex<T>::type* __restrict__ Sbuf, typename Complex<T>::type* __restrict__ Zout,
-    const int* __restrict__ wave_start, const OlaRow* __restrict__ wave_rows, int64_t half, int64_t sum_len,
-    int nwaves, Twiddle2<typename Complex<T>::type> tw2) {
-  using C = typename Complex<T>::type;
-  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x) * 4 + static_cast<int>(threadIdx.x >> 6));
-  if (wave >= nwaves) return;
-  const int64_t seg = blockIdx.y;
-  const int p = wave * 64 + static_cast<int>(threadIdx.x & 63);
-  const int q = static_cast<int>(half) - p;
-  const rsrc_t rs = make_rsrc(Sbuf + seg * sum_len, static_cast<uint32_t>(sum_len * sizeof(C)));
-  const int a0 = __builtin_amdgcn_readfirstlane(wave_start[2 * wave]);
-  const int a1 = __builtin_amdgcn_readfirstlane(wave_start[2 * wave + 1]);
-  const int a2 = __builtin_amdgcn_readfirstlane(wave_start[2 * wave + 2]);
-  C A = ola_side<C>(rs, wave_rows, a0, a1, p);
-  C B = ola_side<C>(rs, wave_rows, a1, a2, q);
-  if (p > half / 2) return;
-  if (p == 0) {   // DC and Nyquist: real parts only (irfft convention)
-    A.y = 0;
-    B.y = 0;
-  }
-  const C w = c_conj(tw2(p));   // exp(+2 pi i p / N)
-  const C Bc = c_conj(B), Ac = c_conj(A);
-  C* Zs = Zout + seg * half;
-  Zs[p] = c_add(c_add(A, Bc), c_mul_si<+1>(c_mul(w, c_sub(A, Bc))));
-  if (p > 0 && q != p) Zs[q] = c_add(c_add(B, Ac), c_mul_si<-1>(c_mul(c_conj(w), c_sub(B, Ac))));
-}
-
-// Row statistics read back from Y (rows too long for one workgroup): one
-// workgroup per row, fixed-order partial sums and a fixed tree.
-template <typename T>
-__global__ __launch_bounds__(256) void k_row_stats(const typename Complex<T>::type* __restrict__ Y,
-                                                   typename Complex<T>::type* __restrict__ stats, int64_t n_out) {
-  using C = typename Complex<T>::type;
-  __shared__ T se[256], sm[256];
-  const C* row = Y + int64_t(blockIdx.x) * n_out;
-  T e = 0, m = 0;
-  for (int64_t i = threadIdx.x; i < n_out; i += 256) {
-    const C v = row[i];
-    const T a = v.x * v.x + v.y * v.y;
-    e += a;
-    m = fmax(m, a);
-  }
-  se[threadIdx.x] = e;
-  sm[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) {
-      se[threadIdx.x] += se[threadIdx.x + w];
-      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) stats[blockIdx.x] = C{se[0], sm[0]};
-}
-
-// Plane scores and the best plane of each segment (one workgroup per
-// segment): energy sums a plane's row energies, peak takes their maximum; the
-// first plane with the largest score wins and a NaN score never does.
-template <typename T>
-__global__ __launch_bounds__(256) void k_plane_best(const typename Complex<T>::type* __restrict__ stats,
-                                                    int rows_per_plane, int planes, int peak,
-                                                    T* __restrict__ score, int* __restrict__ best) {
-  using C = typename Complex<T>::type;
-  __shared__ T red[256];
-  const int64_t seg = blockIdx.x;
-  const C* st = stats + seg * int64_t(rows_per_plane) * planes;
-  T top = 0;
-  int arg = -1;
-  for (int p = 0; p < planes; ++p) {
-    T a = 0;
-    for (int k = threadIdx.x; k < rows_per_plane; k += 256) {
-      const C v = st[int64_t(p) * rows_per_plane + k];
-      a = peak ? fmax(a, v.y) : a + v.x;
-    }
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (int(threadIdx.x) < w)
-        red[threadIdx.x] = peak ? fmax(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
-      __syncthreads();
-    }
-    const T sc = red[0];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      if (score != nullptr) score[seg * planes + p] = sc;
-      if (sc == sc && (arg < 0 || sc > top)) {
-        top = sc;
-        arg = p;
-      }
-    }
-  }
-  if (threadIdx.x == 0) best[seg] = arg < 0 ? 0 : arg;
-}
-
-// y_best[seg] = plane best[seg] of y[seg], copied in 16-byte units.
-__global__ __launch_bounds__(256) void k_gather_plane(const uint4* __restrict__ y, const int* __restrict__ best,
-                                                      uint4* __restrict__ out, int64_t plane_units, int planes) {
-  const int64_t seg = blockIdx.y;
-  const int b = best[seg];
-  const uint4* src = y + (seg * planes + b) * plane_units;
-  uint4* dst = out + seg * plane_units;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < plane_units; i += int64_t(gridDim.x) * 256)
-    dst[i] = src[i];
-}
-
-}  // namespace qtam
+#include "row_kernels.hpp"
+#include "spectrum_kernels.hpp"
 
 // ===========================================================================
 // Host side: plan object, dispatch, C ABI
