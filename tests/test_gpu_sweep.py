@@ -106,3 +106,17 @@ def test_sweep_errors_and_empty(torch_dev):
     assert ys[0].shape == (0, 16, a.N_out)
     with pytest.raises(ValueError):
         qt.forward_sweep([], x)
+
+
+def test_sweep_with_composite_and_regularised_plans(torch_dev):
+    """Plans of other kinds share the spectrum too: a composite bank, a
+    regularised (stop-band) plan with whole-band rows and a Kaiser plan."""
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    fs, n = 1024.0, 4096
+    plans = [qt.Plan(fs, n, 1.0, 10.0, 400.0, 16, planes=[(4.0, "bisquare", 0.0), (8.0, "hann", 0.0)]),
+             qt.Plan(fs, n, 8.0, 10.0, 400.0, 16, window_eps=1e-2),
+             qt.Plan(fs, n, 6.0, 20.0, 500.0, 24, window="kaiser", window_param=6.0)]
+    x = torch.from_numpy(synthetic.batched_segments(3, n, fs, dtype=np.float64)).float().cuda()
+    for p, y in zip(plans, qt.forward_sweep(plans, x)):
+        assert torch.equal(y, p.forward(x)), (p.R, p.N_out)
