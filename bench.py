@@ -5,7 +5,12 @@ Workload (the batched form): 256 segments x 131072 samples (32 s at 4096 Hz) of
 seeded coloured Gaussian noise with an injected chirp and two sine-Gaussian
 glitches each; 256 log-spaced rows from 10 to 2048 Hz; Q in {4, 8, 16}, each
 its own plan; FP32. One step = forward + inverse of the whole batch under each
-of the three plans. Inputs are resident in HBM before timing starts.
+of the three plans (the forward as one sweep that computes each segment's
+spectrum once for the three). Inputs are resident in HBM before timing starts.
+
+`--workload one|precision|diff` times the other workloads instead (one
+segment; 32 x 256 s at 8192 Hz; the differentiable denoiser's training step),
+with their error against the oracle on a sample; `--serving` the serving loop.
 
 Prints one JSON line (rank 0). Extra fields: latency percentiles of a step,
 per-kernel times measured with HIP events on the launch stream, the roofline of
@@ -50,6 +55,8 @@ def parse():
                     help="time each plan's own forward (its own spectrum) instead of the forward sweep")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the short timing of the other forward form (profiling runs)")
+    ap.add_argument("--workload", default="batched", choices=["batched", "one", "precision", "diff"],
+                    help="which workload to time (batched: the default benchmark)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of 1 GiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -130,6 +137,8 @@ def main():
         return serving_main(args)
     if args.copy_probe:
         return copy_probe()
+    if args.workload != "batched":
+        return other_workload(args)
 
     import torch
     import paper_2603_29785_amd as qt
@@ -293,6 +302,103 @@ def main():
         out["composite"] = composite_leg(args, x, B, W, ms_per_step)
     if not args.no_cpu:
         out.update(cpu_leg(args, plans, x_host, x, B, W))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+OTHER_WORKLOADS = {
+    "one": dict(fs=4096.0, n=16384, batch=1, rows=64, q=8.0, f_min=20.0, f_max=1000.0,
+                what="one segment: 4 s at 4096 Hz, white noise + sine-Gaussian (100 Hz, Q 8, SNR 20); Q 8, "
+                     "64 rows 20-1000 Hz"),
+    "precision": dict(fs=8192.0, n=2097152, batch=32, rows=512, q=12.0, f_min=5.0, f_max=4096.0,
+                      what="long segments: 32 x 256 s at 8192 Hz, coloured noise + chirp + 2 sine-Gaussians; "
+                           "Q 12, 512 rows 5-4096 Hz"),
+    "diff": dict(fs=4096.0, n=32768, batch=64, rows=128, q=8.0, f_min=20.0, f_max=2000.0,
+                 what="differentiable denoiser: 64 x 8 s at 4096 Hz; forward, per-row gain x soft threshold, "
+                      "inverse, MSE against the clean signal, backward through the adjoint kernels; Q 8, "
+                      "128 rows 20-2000 Hz"),
+}
+
+
+def other_workload(args):
+    """One of the other workloads: steps timed with HIP events, samples/s,
+    latency, and the error against the FP64 oracle on one segment."""
+    import torch
+    import paper_2603_29785_amd as qt
+    import synthetic
+    from oracle import oracle as o
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    W = OTHER_WORKLOADS[args.workload]
+    B, n, fs = W["batch"], W["n"], W["fs"]
+    fp64 = args.precision == "fp64"
+    rdt = torch.float64 if fp64 else torch.float32
+    plan = qt.Plan(fs, n, W["q"], W["f_min"], W["f_max"], W["rows"], precision=args.precision)
+    stream = torch.cuda.current_stream()
+    if args.workload == "one":
+        x_host = synthetic.single_segment()[None, :]
+    elif args.workload == "precision":
+        x_host = synthetic.batched_segments(B, n, fs, workload=4, dtype=np.float64)
+    else:
+        x_host, clean_host = synthetic.differentiable_pairs(B, n, fs, dtype=np.float64)
+    x = torch.from_numpy(x_host).to(device="cuda", dtype=rdt)
+    if args.workload == "diff":
+        from paper_2603_29785_amd.autograd import GainThresholdDenoiser
+        clean = torch.from_numpy(clean_host).to(device="cuda", dtype=rdt)
+        noise = torch.from_numpy(synthetic.coloured(n, fs, synthetic.rng_for(5, 10_000))).to(device="cuda",
+                                                                                          dtype=rdt)
+        model = GainThresholdDenoiser(plan, 3.0 * plan.forward(noise).abs().median(dim=-1).values)
+        xin = x.clone().requires_grad_(True)
+
+        def step():
+            model.zero_grad(set_to_none=True)
+            xin.grad = None
+            loss = torch.mean((model(xin) - clean) ** 2)
+            loss.backward()
+    else:
+        ws = torch.empty(plan.workspace_bytes(B), dtype=torch.uint8, device="cuda")
+        y = torch.empty((B, plan.R, plan.N_out), dtype=torch.complex128 if fp64 else torch.complex64, device="cuda")
+        xr = torch.empty_like(x)
+
+        def step():
+            plan.forward(x, out=y, ws=ws, stream=stream)
+            plan.inverse(y, out=xr, ws=ws, stream=stream)
+    steps = args.steps if args.workload != "one" else max(args.steps, 200)
+    for _ in range(max(args.warmup, 2)):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    ms = 1e3 * wall / steps
+    out = {"metric": "fwd+inv QTAM samples/s @1 GPU; p50/p99 latency; recon rel-err vs FP64",
+           "value": B * n / (ms * 1e-3), "unit": "samples/s", "n_gpus": 1, "steps": steps,
+           "warmup": max(args.warmup, 2), "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if fp64 else "f32", "data": "synthetic",
+           "config": {"workload": W["what"], "batch": B, "n_samples": n, "fs": fs, "q": W["q"],
+                      "rows": W["rows"], "f_min": W["f_min"], "f_max": W["f_max"], "n_out": plan.N_out,
+                      "precision": args.precision},
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                          "what": "one step, HIP events"}}
+    # error of segment 0 against the oracle (same input bits)
+    op = o.OraclePlan(fs=fs, n=n, q=W["q"], f_min=W["f_min"], f_max=W["f_max"], rows=W["rows"])
+    x0 = x[0].double().cpu().numpy()
+    Yo = op.forward(x0)
+    Yg = plan.forward(x[0:1].contiguous())[0].cpu().numpy()
+    Yc = Yo.astype(np.complex128 if fp64 else np.complex64)   # the oracle's coefficients in device precision
+    xg = plan.inverse(torch.from_numpy(Yc[None]).to("cuda"))[0].cpu().numpy()
+    xo = op.inverse(Yc.astype(np.complex128))
+    out["recon_rel_err"] = {"coef": float(np.linalg.norm(Yg - Yo) / np.linalg.norm(Yo)),
+                            "recon": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
+                            "segments": 1, "vs": "FP64 CPU oracle", "precision": args.precision}
     print(json.dumps(out), flush=True)
     return 0
 
