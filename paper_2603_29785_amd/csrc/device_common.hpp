@@ -35,7 +35,8 @@ template <typename T> constexpr int elems_per_thread() { return sizeof(T) == 4 ?
 
 template <typename T, int L>
 struct RowGeom {
-  static constexpr int E = L < elems_per_thread<T>() ? L : elems_per_thread<T>();
+  static constexpr int E0 = L < elems_per_thread<T>() ? L : elems_per_thread<T>();
+  static constexpr int E = L / E0 > 1024 ? L / 1024 : E0;   // at most 1024 threads per transform
   static constexpr int TPR = L / E;
   static constexpr int G = TPR >= 256 ? 1 : 256 / TPR;   // transforms per workgroup
   static constexpr int NT = G * TPR;

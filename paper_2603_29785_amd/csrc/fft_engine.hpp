@@ -235,12 +235,27 @@ enum TwiddleMode { TW_POW = 0, TW_FULL = 1, TW_MIXED = 2 };
 constexpr int kFullStride = 16;
 constexpr bool tw_full_pass(int mode, int ns) { return mode == TW_FULL || (mode == TW_MIXED && ns <= kFullStride); }
 
+// LDS a transform of length L needs: the padded exchange region, or half of
+// it when the whole one would not fit the 160 KiB of a workgroup (the
+// exchanges then go in two rounds, one per half of the destination indices).
+template <typename T, int L>
+constexpr bool fft_split() {
+  return size_t(lds_size(L)) * sizeof(typename Complex<T>::type) > 160u * 1024u;
+}
+template <typename T, int L>
+constexpr int fft_lds_elems() {
+  return fft_split<T, L>() ? lds_size(L / 2) : lds_size(L);
+}
+
 template <typename T, int L, int E, int S, int TW = TW_POW>
 struct BlockFft {
   using C = typename Complex<T>::type;
-  static_assert((L & (L - 1)) == 0 && (E & (E - 1)) == 0 && E <= L && E <= 16, "pow2 sizes");
+  static_assert((L & (L - 1)) == 0 && (E & (E - 1)) == 0 && E <= L && E <= 32, "pow2 sizes");
   static constexpr int TPR = L / E;
-  static constexpr int radix(int ns) { return (L / ns >= E) ? E : L / ns; }
+  static constexpr int RMAX = E < 16 ? E : 16;   // butterflies of at most radix 16; E = 32 holds two groups
+  static constexpr int radix(int ns) { return (L / ns >= RMAX) ? RMAX : L / ns; }
+  static constexpr bool SPLIT = fft_split<T, L>();
+  static constexpr int WN = E > 16 ? 16 : E;     // twiddle registers: one group at a time when E > 16
   static constexpr int last_ns() {
     int ns = 1;
     while (ns * radix(ns) < L) ns *= radix(ns);
@@ -263,6 +278,13 @@ struct BlockFft {
     return off;
   }
   static constexpr int tw_size() { return tw_offset(L); }
+  // registers of a radix-R2 pass whose input index lies below L/2
+  static constexpr int lower_reads(int r2) {
+    int n = 0;
+    for (int q = 0; q < E / r2; ++q)
+      for (int r = 0; r < r2; ++r) n += (q * TPR + r * (L / r2) < L / 2) ? 1 : 0;
+    return n;
+  }
 
   __device__ static __forceinline__ int in_index(int tl, int i) {
     return tl + (i / R0) * TPR + (i % R0) * (L / R0);
@@ -272,17 +294,19 @@ struct BlockFft {
   }
 
   // Twiddles of the pass with stride NS for this thread: w[q*R + r], r >= 1,
-  // from the base powers w^1, w^2, w^4, w^8.
+  // from the base powers w^1, w^2, w^4, w^8 (groups q0 .. q1-1, stored from
+  // w[0] on when only one group is held at a time).
   template <int NS>
-  __device__ static __forceinline__ void load_twiddles(C (&w)[E], int tl, rsrc_t tw) {
+  __device__ static __forceinline__ void load_twiddles(C (&w)[WN], int tl, rsrc_t tw, int q0 = 0,
+                                                       int q1 = E / radix(NS)) {
     constexpr int R = radix(NS);
 #pragma unroll
-    for (int q = 0; q < E / R; ++q) {
+    for (int q = q0; q < q1; ++q) {
       const uint32_t k = static_cast<uint32_t>((tl + q * TPR) & (NS - 1));
       if constexpr (tw_full_pass(TW, NS)) {
 #pragma unroll
         for (int r = 1; r < R; ++r)
-          w[q * R + r] = bload<C>(tw, k * sizeof(C), (tw_offset(NS) + (r - 1) * NS) * sizeof(C));
+          w[(q - q0) * R + r] = bload<C>(tw, k * sizeof(C), (tw_offset(NS) + (r - 1) * NS) * sizeof(C));
       } else {
         C a[16];
 #pragma unroll
@@ -299,7 +323,7 @@ struct BlockFft {
           for (int r = 9; r < 16; ++r) a[r] = c_mul(a[8], a[r - 8]);
         }
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[q * R + r] = a[r];
+        for (int r = 1; r < R; ++r) w[(q - q0) * R + r] = a[r];
       }
     }
   }
@@ -308,15 +332,17 @@ struct BlockFft {
   // applied, then the butterflies; unless it was the last pass the values
   // are exchanged through LDS into the next pass's order.
   template <int NS>
-  __device__ static __forceinline__ void pass(C (&v)[E], C (&w)[E], C* lds, int tl, rsrc_t tw, int nz) {
+  __device__ static __forceinline__ void pass(C (&v)[E], C (&w)[WN], C* lds, int tl, rsrc_t tw, int nz) {
     constexpr int R = radix(NS);
-    if constexpr (NS > 1) load_twiddles<NS>(w, tl, tw);
+    constexpr bool kAll = WN == E;   // all groups' twiddles at once, else one group at a time
+    if constexpr (NS > 1 && kAll) load_twiddles<NS>(w, tl, tw);
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
       if constexpr (NS > 1) {
+        if constexpr (!kAll) load_twiddles<NS>(w, tl, tw, q, q + 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C t = w[q * R + r];
+          C t = w[(kAll ? q * R : 0) + r];
           if constexpr (S > 0) t.y = -t.y;
           v[q * R + r] = c_mul(v[q * R + r], t);
         }
@@ -332,22 +358,68 @@ struct BlockFft {
     if constexpr (NS * R < L) {
       constexpr int NS2 = NS * R;
       constexpr int R2 = radix(NS2);
+      if constexpr (!SPLIT) {
 #pragma unroll
-      for (int q = 0; q < E / R; ++q) {
-        const int j = tl + q * TPR;
-        const int k = j & (NS - 1);
-        const int base = (j - k) * R + k;
+        for (int q = 0; q < E / R; ++q) {
+          const int j = tl + q * TPR;
+          const int k = j & (NS - 1);
+          const int base = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = v[q * R + r];
+          for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = v[q * R + r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < E / R2; ++q) {
+          const int j = tl + q * TPR;
+#pragma unroll
+          for (int r = 0; r < R2; ++r) v[q * R2 + r] = lds[lds_pad(j + r * (L / R2))];
+        }
+        __syncthreads();
+      } else {
+        // The LDS region holds half of the indices. With two register groups
+        // per pass (E = 2R) and NS dividing TPR, group 0 holds exactly the
+        // values bound for indices below L/2 and group 1 the others, and a
+        // value bound for register (q, r) of the next pass comes from below
+        // L/2 iff q TPR + r L/R2 < L/2 (tl < TPR; both terms are multiples of
+        // TPR). Round 0 moves the lower half (into tmp, since the registers it
+        // fills may still hold group-1 values), round 1 the upper half.
+        static_assert(E / R == 2 && TPR % NS == 0 && lower_reads(R2) == E / 2, "split exchange layout");
+        constexpr int H = L / 2;
+        C tmp[E / 2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          {
+            const int j = tl + h * TPR;
+            const int k = j & (NS - 1);
+            const int base = (j - k) * R + k - h * H;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS)] = v[h * R + r];
+          }
+          __syncthreads();
+          int n = 0;
+#pragma unroll
+          for (int q = 0; q < E / R2; ++q) {
+#pragma unroll
+            for (int r = 0; r < R2; ++r) {
+              const int off = q * TPR + r * (L / R2);   // compile-time after unrolling
+              if ((off < H) == (h == 0)) {
+                const C x = lds[lds_pad(tl + off - h * H)];
+                if (h == 0) tmp[n++] = x;
+                else v[q * R2 + r] = x;
+              }
+            }
+          }
+          __syncthreads();
+        }
+        int n = 0;
+#pragma unroll
+        for (int q = 0; q < E / R2; ++q) {
+#pragma unroll
+          for (int r = 0; r < R2; ++r) {
+            if (q * TPR + r * (L / R2) < H) v[q * R2 + r] = tmp[n++];
+          }
+        }
       }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < E / R2; ++q) {
-        const int j = tl + q * TPR;
-#pragma unroll
-        for (int r = 0; r < R2; ++r) v[q * R2 + r] = lds[lds_pad(j + r * (L / R2))];
-      }
-      __syncthreads();
       pass<NS2>(v, w, lds, tl, tw, 0);
     }
   }
@@ -359,7 +431,7 @@ struct BlockFft {
   // v[0], v[1], v[14], v[15] (4): that pass then skips the zero terms, with
   // the same results; any other value runs the full transform.
   __device__ static __forceinline__ void run(C (&v)[E], C* lds, int tl, rsrc_t tw, int nz = 0) {
-    C w[E];
+    C w[WN];
     pass<1>(v, w, lds, tl, tw, nz);
   }
   // offsets of register element i from the thread's own index tl

@@ -63,6 +63,10 @@ enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3, T_DENSE = 4, T_TILE 
 
 constexpr int kMaxLog2Single32 = 14;   // LDS-resident FFT up to 16384 points (FP32)
 constexpr int kMaxLog2Single64 = 13;   // and 8192 points (FP64)
+// Envelope rows in one workgroup: up to 32768 points in FP32 (1024 threads x
+// 32 values, exchanges through LDS in two halves), 8192 in FP64.
+constexpr int kMaxLog2Rows32 = 15;
+constexpr int kMaxLog2Rows64 = 13;
 
 int ilog2(int64_t v) {
   int l = 0;
@@ -190,7 +194,8 @@ void twiddles_strided(std::vector<T>& out, int64_t count, int64_t step, int64_t 
 template <typename T>
 void stockham_twiddles(std::vector<T>& out, int64_t L, int64_t e, int mode) {
   out.clear();
-  auto radix = [&](int64_t ns) { return (L / ns >= e) ? e : L / ns; };
+  const int64_t rmax = std::min<int64_t>(e, 16);   // butterflies of at most radix 16
+  auto radix = [&](int64_t ns) { return (L / ns >= rmax) ? rmax : L / ns; };
   for (int64_t ns = 1; ns < L; ns *= radix(ns)) {
     const int64_t R = radix(ns);
     if (ns == 1) continue;
@@ -205,7 +210,12 @@ void stockham_twiddles(std::vector<T>& out, int64_t L, int64_t e, int mode) {
   if (out.empty()) out.assign(2, T(0));
 }
 
-int64_t engine_e(int64_t L, bool f64) { return std::min<int64_t>(L, f64 ? 8 : 16); }
+// Values per thread of a length-L block transform (as RowGeom: at most 1024
+// threads per transform).
+int64_t engine_e(int64_t L, bool f64) {
+  const int64_t e = std::min<int64_t>(L, f64 ? 8 : 16);
+  return L / e > 1024 ? L / 1024 : e;
+}
 
 struct Blob {
   std::vector<char> bytes;
@@ -432,7 +442,7 @@ struct Timed {
 // Dispatch over compile-time sizes
 // ---------------------------------------------------------------------------
 #define QTAM_POW2_CASES(X) \
-  X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+  X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 
 template <typename T, int S>
 bool launch_fft_rows(int log2l, const void* in, void* out, int64_t count, int64_t stride, const void* tw,
@@ -534,7 +544,7 @@ bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* o
   switch (log2l) {
 #define X(LG)                                                                                          \
   case LG:                                                                                             \
-    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Single32 : kMaxLog2Single64)) {                    \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Rows32 : kMaxLog2Rows64)) {                        \
       using Geo = RowGeom<T, (1 << LG)>;                                                               \
       const int blocks = static_cast<int>((total_rows + Geo::G - 1) / Geo::G);                         \
       if (forward) {                                                                                   \
@@ -1056,7 +1066,7 @@ void choose_geometry(qtam_plan_s* pl) {
   pl->m2 = hp.half / pl->radix_r;
   const int ln = ilog2(hp.n_out);
   if (ln < 2) return;
-  pl->big_rows = !pl->bluestein && ln > max_single;
+  pl->big_rows = !pl->bluestein && ln > (f64 ? kMaxLog2Rows64 : kMaxLog2Rows32);
   if (pl->big_rows) {
     const int l2 = ln / 2, l1 = ln - l2;   // N_out = r1 * r2, r1 >= r2
     pl->r1 = int64_t(1) << l1;
@@ -1304,7 +1314,9 @@ qtam_status qtam_tile_inverse(qtam_plan_t pl, const void* y, int32_t row, void* 
   if (batch == 0) return QTAM_OK;
   if (!y || !x || !ws) return QTAM_ERR_INVALID_ARG;
   if (!pl->gpu_supported) return pl->unsupported_reason;
-  if (pl->big_rows || pl->bluestein) return QTAM_ERR_UNSUPPORTED;
+  if (pl->big_rows || pl->bluestein ||
+      ilog2(pl->hp.n_out) > (pl->hp.precision == QTAM_FP64 ? kMaxLog2Single64 : kMaxLog2Single32))
+    return QTAM_ERR_UNSUPPORTED;
   if (!pl->device) return QTAM_ERR_INVALID_ARG;
   const int64_t chunk = std::min<int64_t>(chunk_for(pl, batch, ws_bytes), 65535);
   if (chunk < 1) return QTAM_ERR_WORKSPACE;

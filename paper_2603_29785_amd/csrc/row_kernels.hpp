@@ -150,7 +150,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
   using Geo = RowGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, +1, TW_MIXED>;
   constexpr bool kWaveRow = Geo::TPR >= 64;   // every lane of a wave is on the same row
-  __shared__ C lds[Geo::G * lds_size(L)];
+  __shared__ C lds[Geo::G * fft_lds_elems<T, L>()];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
   const int u = xcd_major_block(nblocks);
   int gr = u * Geo::G + g;
@@ -222,14 +222,14 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
   // lane of this wave has zeros in first-pass inputs 1..14 (or 2..13) the
   // first pass skips them (same results, fewer operations).
   int nz = 0;
-  if constexpr (kWaveRow && F::R0 == 16) {
+  if constexpr (kWaveRow && F::R0 == 16 && Geo::E == 16) {
     const int jlo = rm.lo - rm.s, jhi = rm.hi - rm.s;
     const int t0 = __builtin_amdgcn_readfirstlane(tl) & ~63;
     constexpr int Q = L / 16;   // input i of lane tl sits at slot tl + i Q
     auto zero = [&](int a, int b) { return t0 + a * Q > jhi && t0 + 63 + b * Q < L + jlo; };
     nz = zero(1, 14) ? 2 : (zero(2, 13) ? 4 : 0);
   }
-  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw), nz);
+  F::run(v, lds + g * fft_lds_elems<T, L>(), tl, F::twiddles(tw), nz);
   const int64_t r0 = int64_t(u) * Geo::G;
   const int64_t nrow = total - r0 < Geo::G ? total - r0 : Geo::G;
   const rsrc_t ry = make_rsrc(Y + r0 * L, static_cast<uint32_t>(nrow * L * sizeof(C)));
@@ -252,7 +252,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
   using Geo = RowGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, -1, TW_MIXED>;
   constexpr bool kWaveRow = Geo::TPR >= 64;
-  __shared__ C lds[Geo::G * lds_size(L)];
+  __shared__ C lds[Geo::G * fft_lds_elems<T, L>()];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
   const int64_t r0 = int64_t(blockIdx.x) * Geo::G;
   const int64_t nrow = total - r0 < Geo::G ? total - r0 : Geo::G;
@@ -276,22 +276,29 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
     unsigned bw = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(T));
     opaque(bs);
     opaque(bw);
-    T w[Geo::E];
+    // (rows of 32 values per thread load them after the transform: registers)
+    constexpr bool kEarly = Geo::E <= 16;
+    T w[kEarly ? Geo::E : 1];
+    if constexpr (kEarly) {
 #pragma unroll
-    for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::out_off(i);
-      const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
-      w[i] = bload<T>(rt, bw + j * static_cast<unsigned>(sizeof(T)));
+      for (int i = 0; i < Geo::E; ++i) {
+        const int off = F::out_off(i);
+        const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
+        w[i] = bload<T>(rt, bw + j * static_cast<unsigned>(sizeof(T)));
+      }
     }
-    F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+    F::run(v, lds + g * fft_lds_elems<T, L>(), tl, F::twiddles(tw));
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
       const int off = F::out_off(i);
       const unsigned j = static_cast<unsigned>(off < L / 2 ? off : off - L);
-      bstore<C, kSStore>(rs, C{v[i].x * w[i], v[i].y * w[i]}, bs + j * static_cast<unsigned>(sizeof(C)));
+      T wi;
+      if constexpr (kEarly) wi = w[i];
+      else wi = bload<T>(rt, bw + j * static_cast<unsigned>(sizeof(T)));
+      bstore<C, kSStore>(rs, C{v[i].x * wi, v[i].y * wi}, bs + j * static_cast<unsigned>(sizeof(C)));
     }
   } else {
-    F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+    F::run(v, lds + g * fft_lds_elems<T, L>(), tl, F::twiddles(tw));
     const int gr = static_cast<int>(r0) + g;
     if (gr >= total) return;
     const int seg = gr / R;
