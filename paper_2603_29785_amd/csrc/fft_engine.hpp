@@ -2,9 +2,10 @@
 //
 // A transform of length L (a power of two) is processed by TPR = L/E threads,
 // each holding E complex values in registers. Every pass applies radix-R
-// butterflies (R = E, the last pass possibly smaller) to values held in
-// registers; between passes the values are exchanged through an LDS region of
-// the transform. First-pass inputs and last-pass outputs are addressed so that
+// butterflies (R = min(E, 16), the last pass possibly smaller; with E = 32 a
+// thread holds two groups) to values held in registers; between passes the
+// values are exchanged through an LDS region of the transform (in two rounds
+// over half of it when the whole would not fit). First-pass inputs and last-pass outputs are addressed so that
 // consecutive threads touch consecutive elements: kernels feed the engine
 // straight from global memory and store its results straight back, coalesced.
 //
