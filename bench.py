@@ -239,7 +239,7 @@ def main():
                 k["total_ms"] += ms
                 k["launches"] += cnt
                 kb = kernel_bytes(name, p, B, b)
-                k["bytes"] += (kb or 0.0) * cnt
+                k["bytes"] += (kb or 0.0) * reps   # one call per plan and step covers the batch (in chunks)
             p.timing(False)
         for name, k in kernels.items():
             k["avg_ms"] = k["total_ms"] / max(k["launches"], 1)
