@@ -2,7 +2,7 @@
 
 * dot-product identities <F x, g> = <x, F^T g> and <G y, z> = <y, G^T z> at the
   differentiable workload's full size (64 x 32768 samples, Q = 8, 128 rows,
-  20-2000 Hz);
+  20-2000 Hz) and on rows of 32768 points;
 * the adjoints against the oracle's explicit transposes on a tiny plan
   (matrices built column by column from the FP64 CPU oracle);
 * torch.autograd.gradcheck on a tiny FP64 plan, and central finite
@@ -47,6 +47,32 @@ def test_dot_product_identities_full_size(torch_dev, precision, tol):
     assert abs(lhs - rhs) <= tol * max(abs(lhs), 1.0) * 10, (lhs, rhs)
     y = torch.randn(B, p.R, p.N_out, device="cuda", dtype=cdt, generator=g)
     z = torch.randn(B, 32768, device="cuda", dtype=rdt, generator=g)
+    lhs = float(torch.sum(p.inverse(y).double() * z.double()))
+    rhs = vdot_real(y.to(torch.complex128), p.inverse_adjoint(z).to(torch.complex128))
+    assert abs(lhs - rhs) <= tol * max(abs(lhs), 1.0) * 10, (lhs, rhs)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-12)])
+def test_dot_product_identities_long_rows(torch_dev, precision, tol):
+    """Rows of 32768 points: one workgroup per row in FP32, the two-pass form
+    through the workspace in FP64; both adjoints."""
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    n = 1 << 20
+    p = qt.Plan(16384.0, n, 8.0, 20.0, 4000.0, 64, precision=precision)
+    assert p.N_out == 32768
+    print("long-row adjoints", precision, flush=True)
+    rdt = torch.float64 if precision == "fp64" else torch.float32
+    cdt = torch.complex128 if precision == "fp64" else torch.complex64
+    g = torch.Generator(device="cuda").manual_seed(2)
+    B = 2
+    x = torch.randn(B, n, device="cuda", dtype=rdt, generator=g)
+    gy = torch.randn(B, p.R, p.N_out, device="cuda", dtype=cdt, generator=g)
+    lhs = vdot_real(p.forward(x).to(torch.complex128), gy.to(torch.complex128))
+    rhs = float(torch.sum(x.double() * p.forward_adjoint(gy).double()))
+    assert abs(lhs - rhs) <= tol * max(abs(lhs), 1.0) * 10, (lhs, rhs)
+    y = torch.randn(B, p.R, p.N_out, device="cuda", dtype=cdt, generator=g)
+    z = torch.randn(B, n, device="cuda", dtype=rdt, generator=g)
     lhs = float(torch.sum(p.inverse(y).double() * z.double()))
     rhs = vdot_real(y.to(torch.complex128), p.inverse_adjoint(z).to(torch.complex128))
     assert abs(lhs - rhs) <= tol * max(abs(lhs), 1.0) * 10, (lhs, rhs)
