@@ -151,6 +151,27 @@ def test_long_row_composite_statistics(torch_dev):
     check_selection(gp, op, Y, M, Yo, "energy", "fp32")
 
 
+def test_composite_statistics_rows_32768(torch_dev):
+    """Rows of 32768 points run in one workgroup (FP32): statistics taken from
+    the registers of a 1024-thread transform."""
+    torch = torch_dev
+    print("composite rows 32768", flush=True)
+    planes = [(2.0, "bisquare", 0.0), (6.0, "hann", 0.0)]
+    gp, op = plans(planes, "fp32", fs=4096.0, n=262144, f_min=200.0, f_max=1000.0, rows=8, cap_mode=o.CAP_NONE)
+    assert gp.N_out == 32768
+    x = synthetic.batched_segments(2, gp.N, 4096.0, workload=23)
+    xd, xh = device_signal(torch, x, "fp32")
+    Y, M = gp.forward_metric(xd)
+    Yo = op.forward(xh)
+    assert rel_rows(Y.cpu().numpy(), Yo).max() <= 1e-5
+    assert torch.equal(Y, gp.forward(xd))
+    e_o, p_o = op.row_stats(Yo)
+    Mg = M.cpu().numpy()
+    assert np.abs(Mg.real / e_o - 1).max() <= 1e-5
+    assert np.abs(Mg.imag / p_o - 1).max() <= 1e-4
+    check_selection(gp, op, Y, M, Yo, "peak", "fp32")
+
+
 def test_selection_empty_and_errors(torch_dev):
     torch = torch_dev
     import paper_2603_29785_amd as qt
