@@ -219,7 +219,12 @@ class Plan:
         p.norm_mode = NORM[norm_mode] if isinstance(norm_mode, str) else int(norm_mode)
         p.n_out = int(n_out)
         p.p_floor_rel = float(p_floor_rel)
-        p.precision = FP64 if precision in ("fp64", FP64, "float64") else FP32
+        if precision in ("fp64", "float64", FP64):
+            p.precision = FP64
+        elif precision in ("fp32", "float32", FP32):
+            p.precision = FP32
+        else:
+            raise ValueError("precision must be 'fp32' or 'fp64', got %r" % (precision,))
         p.flags = PLAN_HOST_ONLY if host_only else 0
         p.window_eps = float(window_eps)
         if planes:

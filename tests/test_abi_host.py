@@ -244,3 +244,10 @@ def test_regularised_plan_tables_match_oracle():
     assert L.qtam_tile_inverse(reg._h, d, 0, d, 0, d, 1 << 20, None) == binding.QTAM_OK
     with pytest.raises(qt.QtamError):
         host_plan(window_eps=-1.0, **kw)
+
+
+def test_unknown_precision_rejected():
+    with pytest.raises(ValueError):
+        host_plan(sample_rate=1024.0, n_samples=4096, q=8.0, f_min=10.0, f_max=400.0, n_rows=16, precision="fp16")
+    assert host_plan(sample_rate=1024.0, n_samples=4096, q=8.0, f_min=10.0, f_max=400.0, n_rows=16,
+                     precision="float64").fp64
