@@ -44,9 +44,13 @@ struct RowGeom {
 
 // Columns per workgroup of the four-step passes: C * L values fill at most
 // 64 KiB of LDS, at least 4 columns for 32/64-byte contiguous runs.
-template <typename T, int L>
+// EP > 0 sets the values per thread (the second four-step pass of the
+// spectrum and synthesis transforms runs faster with 8 in FP32: twice the
+// waves per workgroup for its LDS-staged rows).
+template <typename T, int L, int EP = 0>
 struct ColGeom {
-  static constexpr int E = L < elems_per_thread<T>() ? L : elems_per_thread<T>();
+  static constexpr int E0 = EP > 0 ? EP : elems_per_thread<T>();
+  static constexpr int E = L < E0 ? L : E0;
   static constexpr int TPR = L / E;
   static constexpr int CAP = (65536 / (2 * int(sizeof(T)))) / L;
   static constexpr int CC = CAP >= 16 ? 16 : (CAP >= 4 ? CAP : 4);

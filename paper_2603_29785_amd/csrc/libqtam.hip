@@ -67,6 +67,9 @@ constexpr int kMaxLog2Single64 = 13;   // and 8192 points (FP64)
 // 32 values, exchanges through LDS in two halves), 8192 in FP64.
 constexpr int kMaxLog2Rows32 = 15;
 constexpr int kMaxLog2Rows64 = 13;
+// Values per thread of the second four-step pass of the spectrum and
+// synthesis transforms (its twiddle table, d_tw_n1, is built for it).
+constexpr int kPass2E = 8;
 
 int ilog2(int64_t v) {
   int l = 0;
@@ -293,7 +296,7 @@ qtam_status upload(qtam_plan_s* pl) {
     stockham_twiddles(tw, pl->m2, engine_e(pl->m2, f64), TW_POW);
     o_half = blob.add(tw.data(), tw.size() * sizeof(T));
   } else {
-    stockham_twiddles(tw, pl->n1, engine_e(pl->n1, f64), TW_POW);
+    stockham_twiddles(tw, pl->n1, std::min<int64_t>(pl->n1, kPass2E), TW_POW);
     o_n1 = blob.add(tw.data(), tw.size() * sizeof(T));
     stockham_twiddles(tw, pl->n2, engine_e(pl->n2, f64), TW_POW);
     o_n2 = blob.add(tw.data(), tw.size() * sizeof(T));
@@ -492,7 +495,7 @@ bool launch_fft_cols(int log2l, const void* in, void* out, int64_t n1, int64_t s
   }
 }
 
-template <typename T, int S>
+template <typename T, int S, int EP = 0>
 bool launch_fft_rows_t(int log2l, const void* in, void* out, int64_t n2, int64_t segs, int64_t seg_stride,
                        const void* tw, hipStream_t st) {
   using C = typename Complex<T>::type;
@@ -500,9 +503,9 @@ bool launch_fft_rows_t(int log2l, const void* in, void* out, int64_t n2, int64_t
 #define X(LG)                                                                                       \
   case LG:                                                                                          \
     if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                       \
-      using Geo = ColGeom<T, (1 << LG)>;                                                            \
+      using Geo = ColGeom<T, (1 << LG), EP>;                                                        \
       if (n2 % Geo::CC) return false;                                                               \
-      hipLaunchKernelGGL((k_fft_rows_t<T, (1 << LG), S>), dim3(unsigned(n2 / Geo::CC), unsigned(segs)), \
+      hipLaunchKernelGGL((k_fft_rows_t<T, (1 << LG), S, EP>), dim3(unsigned(n2 / Geo::CC), unsigned(segs)), \
                          dim3(Geo::NT), 0, st, static_cast<const C*>(in), static_cast<C*>(out), n2,  \
                          seg_stride, static_cast<const C*>(tw));                                    \
       return true;                                                                                  \
@@ -522,9 +525,9 @@ bool launch_spec_rows_twist(int log2l, const void* in, void* out, int64_t n2, in
 #define X(LG)                                                                                       \
   case LG:                                                                                          \
     if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                       \
-      using Geo = ColGeom<T, (1 << LG)>;                                                            \
+      using Geo = ColGeom<T, (1 << LG), kPass2E>;                                                   \
       if (n2 % Geo::CC) return false;                                                               \
-      hipLaunchKernelGGL((k_spec_rows_twist<T, (1 << LG)>), dim3(unsigned(n2 / Geo::CC), unsigned(segs)), \
+      hipLaunchKernelGGL((k_spec_rows_twist<T, (1 << LG), kPass2E>), dim3(unsigned(n2 / Geo::CC), unsigned(segs)), \
                          dim3(Geo::NT), 0, st, static_cast<const C*>(in), static_cast<C*>(out), n2,  \
                          seg_stride, static_cast<const C*>(tw), tw2);                               \
       return true;                                                                                  \
@@ -727,7 +730,7 @@ bool transform_m2(qtam_plan_s* pl, const void* in, void* out, void* tmp, int64_t
   }
   if (!ok) return false;
   Timed tm(pl, k_pass2, st);
-  return launch_fft_rows_t<T, S>(ilog2(pl->n1), tmp, out, pl->n2, count, m2, pl->d_tw_n1, st);
+  return launch_fft_rows_t<T, S, kPass2E>(ilog2(pl->n1), tmp, out, pl->n2, count, m2, pl->d_tw_n1, st);
 }
 
 // Radix-r combination of the decimated transforms (S = -1, analysis) or its
