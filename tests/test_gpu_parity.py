@@ -322,7 +322,7 @@ def test_masked_coefficients_inverse(torch_dev):
     assert rel(xr, op.inverse(keep)) <= 1e-12
 
 
-def random_plans(seed, count):
+def random_plans(seed, count, log2n=(7, 16), log2n_odd=(5, 13), row_range=(3, 97), q_range=(2.0, 24.0)):
     """Seeded random plans over the supported shapes: N = r 2^k (r = 1, 3, 5),
     bands from near DC to Nyquist, every window family, automatic, odd
     (chirp-z) and oversized power-of-two N_out; only frames with condition
@@ -334,20 +334,20 @@ def random_plans(seed, count):
     out = []
     while len(out) < count:
         r = int(rng.choice([1, 3, 5]))
-        n = r * 2 ** int(rng.integers(7 if r == 1 else 5, 16 if r == 1 else 13))
+        n = r * 2 ** int(rng.integers(*(log2n if r == 1 else log2n_odd)))
         fs = float(rng.choice([256.0, 1024.0, 4096.0]))
         nyq = fs / 2
         fmin = float(rng.uniform(0.005, 0.2)) * nyq
         fmax = float(rng.choice([nyq, rng.uniform(0.4, 0.95) * nyq]))
         if fmin < 2 * fs / n:          # at least two bins above DC
             continue
-        rows = int(rng.integers(3, 97))
-        q = float(rng.uniform(2.0, 24.0))
+        rows = int(rng.integers(*row_range))
+        q = float(rng.uniform(*q_range))
         wname, wid, wparam = wins[int(rng.integers(len(wins)))]
         host = qt.Plan(fs, n, q, fmin, fmax, rows, window=wname, window_param=wparam, host_only=True)
         kind = int(rng.integers(3))
         n_out = 0 if kind == 0 else (host.info.max_len if kind == 1 else 2 * host.N_out)
-        if n_out and (n_out > 8192 or n_out < 4):
+        if n_out and (n_out > 32768 or n_out < 4 or (kind == 1 and n_out > 8192)):
             continue
         info = host.info
         if not (info.frame_A > 0 and info.frame_B / info.frame_A <= 1e3):
@@ -356,7 +356,8 @@ def random_plans(seed, count):
     return out
 
 
-RANDOM = random_plans(2026, 16)
+RANDOM = random_plans(2026, 16) + random_plans(2027, 8, log2n=(15, 19), log2n_odd=(13, 16), row_range=(16, 257),
+                                                 q_range=(2.0, 8.0))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
