@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (profiling runs)")
+    ap.add_argument("--cpu-cores", type=int, default=16,
+                    help="host processes of the all-cores oracle timing (1: skip it)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--serving", action="store_true",
                     help="run the continuous-batching serving workload instead")
@@ -441,6 +443,45 @@ def composite_leg(args, x, B, W, ms_main):
                     "(Q %s), samples counted once per plane" % (p.R, list(W["qs"]))}
 
 
+def _oracle_worker(job):
+    """One host process of the all-cores oracle timing: forward + inverse of
+    its own segments of the batched workload (FP64) until its time is up.
+    Imports numpy and the oracle only (no GPU)."""
+    import synthetic
+    from oracle import oracle as o
+    W, first, count, seconds, fp32_inputs = job
+    ops = [o.OraclePlan(fs=W["fs"], n=W["n"], q=q, f_min=W["f_min"], f_max=W["f_max"], rows=W["rows"])
+           for q in W["qs"]]
+    xs = synthetic.batched_segments(count, W["n"], W["fs"], first=first, dtype=np.float64)
+    if fp32_inputs:
+        xs = xs.astype(np.float32).astype(np.float64)
+    done, t_oracle = 0, 0.0
+    while t_oracle < seconds:
+        ta = time.perf_counter()
+        ops[done % 3].inverse(ops[done % 3].forward(xs[done % count]))
+        t_oracle += time.perf_counter() - ta
+        done += 1
+    return done, t_oracle
+
+
+def cpu_all_cores_leg(W, prec, cores, seconds):
+    """The same oracle in `cores` host processes at once (one per core, own
+    segments each): samples/s of the whole host."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    # fresh interpreters (spawn): nothing of this GPU process is inherited; a
+    # worker that dies fails the pool instead of being replaced
+    jobs = [(dict(W), 16 * k, 4, seconds, prec == "fp32") for k in range(cores)]
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as pool:
+        futs = [pool.submit(_oracle_worker, j) for j in jobs]
+        out = [f.result(timeout=4 * seconds + 120) for f in futs]
+    done = sum(d for d, _ in out)
+    rate = sum(d * W["n"] / t for d, t in out)   # processes ran concurrently: rates add
+    return {"value": rate, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": "%d segments of %d samples over %d processes (one per core, plans cycling Q=4/8/16), "
+                      "FP64 forward+inverse, %.0f s each" % (done, W["n"], cores, seconds)}
+
+
 def cpu_leg(args, plans, x_host, x_dev, B, W):
     """FP64 oracle on a bounded sample of the workload (single thread), and
     the GPU's error against it on the same segments."""
@@ -483,9 +524,16 @@ def cpu_leg(args, plans, x_host, x_dev, B, W):
            "sample": "%d segments of %d samples (plans cycling Q=4/8/16), FP64 forward+inverse, "
                      "single thread, %.1f s of oracle time" % (done, W["n"], t_oracle),
            "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
-    return {"cpu_baseline": cpu,
-            "recon_rel_err": {"coef_max": max(errs_y), "recon_max": max(errs_x), "segments": done,
-                              "vs": "FP64 CPU oracle", "precision": prec}}
+    res = {"cpu_baseline": cpu,
+           "recon_rel_err": {"coef_max": max(errs_y), "recon_max": max(errs_x), "segments": done,
+                             "vs": "FP64 CPU oracle", "precision": prec}}
+    cores = min(os.cpu_count() or 1, args.cpu_cores)
+    if cores > 1:
+        try:
+            res["cpu_baseline_all_cores"] = cpu_all_cores_leg(W, prec, cores, min(args.cpu_seconds, 8.0))
+        except Exception as e:   # the single-thread baseline above stands on its own
+            res["cpu_baseline_all_cores"] = {"error": repr(e)}
+    return res
 
 
 def serving_main(args):
