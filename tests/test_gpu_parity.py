@@ -178,6 +178,32 @@ def test_batched_workload_sampled(torch_dev, precision):
     assert float(e.max()) <= TOL[precision]
 
 
+def test_batched_sweep_sampled(torch_dev):
+    """The benchmark's step at full size: the Q set {4, 8, 16} as one forward
+    sweep over 256 x 131072 samples, then each plan's inverse; sampled
+    segments of every plan against the oracle, every segment's round trip
+    against the projection onto the plan's mask."""
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    B, n = 256, 131072
+    specs = [plans(4096.0, n, q, 10.0, 2048.0, 256, "fp32") for q in (4.0, 8.0, 16.0)]
+    gps = [g for g, _ in specs]
+    x = synthetic.batched_segments(B, dtype=np.float64)
+    xh = host_input(x, "fp32")
+    xd = to_dev(torch, xh, "fp32")
+    ys = qt.forward_sweep(gps, xd)
+    Xd = torch.fft.rfft(xd.double(), dim=-1)
+    for (gp, op), Y in zip(specs, ys):
+        print("sweep plan Q", gp.params["q"], flush=True)
+        for i in (1, B // 3, B - 2):
+            assert rel(Y[i].cpu().numpy(), op.forward(xh[i])) <= TOL["fp32"], i
+        xr = gp.inverse(Y)
+        xm = torch.fft.irfft(Xd * torch.from_numpy(gp.mask).cuda(), n=n, dim=-1)
+        e = torch.linalg.norm(xr.double() - xm, dim=-1) / torch.linalg.norm(xm, dim=-1)
+        assert float(e.max()) <= TOL["fp32"]
+        del xr, xm
+
+
 def test_linearity_and_determinism(torch_dev):
     torch = torch_dev
     gp, _ = plans(4096.0, 32768, 8.0, 20.0, 2000.0, 128, "fp32")
