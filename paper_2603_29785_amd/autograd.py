@@ -91,7 +91,11 @@ class SoftThresholdGainFn(torch.autograd.Function):
         gy = gg = None
         if ctx.needs_input_grad[0]:
             lam = thresholds[:, None]
-            c = torch.where(m > 0, lam * p / (r * r * r), torch.zeros((), dtype=p.dtype, device=p.device))
+            # lambda p / |Y|^3 as (lambda/|Y|)(p/|Y|)/|Y|: where m > 0 and
+            # lambda > 0, |Y| > lambda and |p| <= |Y| |G|, so no factor
+            # overflows or underflows to 0/0; a zero threshold adds nothing
+            c = torch.where((m > 0) & (lam > 0), (lam / r) * (p / r) / r,
+                            torch.zeros((), dtype=p.dtype, device=p.device))
             g = gain[:, None]
             gy = torch.view_as_complex(torch.addcmul(gr * (m * g)[..., None], yr, (c * g)[..., None]))
         if ctx.needs_input_grad[1]:

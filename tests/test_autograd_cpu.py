@@ -63,3 +63,37 @@ def test_gain_only_and_input_only():
     y1 = y.clone().requires_grad_(True)
     soft_threshold_gain(y1, gain, lam).abs().sum().backward()
     assert y1.grad is not None and y1.grad.shape == y.shape
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_zero_thresholds_and_tiny_envelopes(dtype):
+    """Rows with a zero threshold (gain only) and envelope values that are 0
+    or far below every threshold: the gradient stays finite and equals the
+    composed autograd one."""
+    y, gain, lam = inputs((2, 5, 12), dtype, 4)
+    lam[1] = 0.0
+    lam[3] = 0.0
+    y[..., 0] = 0
+    y[..., 1] = 1e-20
+    y[:, 3, 2] = 1e-30 + 0j
+    ya, ga = y.clone().requires_grad_(True), gain.clone().requires_grad_(True)
+    yb, gb = y.clone().requires_grad_(True), gain.clone().requires_grad_(True)
+    out_a = soft_threshold_gain(ya, ga, lam)
+    out_b = composed(yb, gb, lam)
+    assert torch.isfinite(torch.view_as_real(out_a)).all()
+    w = torch.randn(out_a.shape, generator=torch.Generator().manual_seed(5), dtype=out_a.dtype)
+    (out_a * w.conj()).real.sum().backward()
+    (out_b * w.conj()).real.sum().backward()
+    assert torch.isfinite(torch.view_as_real(ya.grad)).all() and torch.isfinite(ga.grad).all()
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    # autograd through |Y| itself turns NaN at |Y| = 1e-20 in FP32 (the
+    # square underflows); there the mask is locally constant (1 on a zero
+    # threshold row, 0 elsewhere), so the gradient is m g G
+    fin = torch.isfinite(torch.view_as_real(yb.grad)).all(-1)
+    scale = float(yb.grad[fin].abs().max())
+    assert float((ya.grad - yb.grad)[fin].abs().max()) <= tol * scale
+    m = (lam[:, None] == 0).to(dtype).expand(y.shape)
+    closed = w * (gain[:, None] * m)
+    if (~fin).any():
+        assert float((ya.grad - closed)[~fin].abs().max()) <= tol * scale
+    assert torch.allclose(ga.grad, gb.grad, rtol=tol, atol=tol * float(gb.grad.abs().max()))
