@@ -168,6 +168,32 @@ def _arr(ptr, n, dtype):
     return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
 
 
+def expect_tensor(t, shape, dtype, device, what: str):
+    """Raises ValueError unless t is a contiguous tensor of exactly this shape
+    and dtype on this device: the library is handed only a base pointer and
+    writes every element of the expected shape through it."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a tensor" % what)
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s tensor of shape %s on %s; got %s %s on %s%s" % (
+            what, dtype, tuple(shape), device, t.dtype, tuple(t.shape), t.device,
+            "" if t.is_contiguous() else " (not contiguous)"))
+    return t
+
+
+def expect_workspace(ws, device):
+    """Raises ValueError unless ws is a contiguous tensor on `device` (its
+    byte size, numel * element_size, is passed to the library, which checks
+    it against what the call needs)."""
+    import torch
+    if not isinstance(ws, torch.Tensor) or ws.device != device or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous tensor on %s; got %s" % (
+            device, ("%s tensor on %s" % (tuple(ws.shape), ws.device)) if isinstance(ws, torch.Tensor)
+            else type(ws).__name__))
+    return ws
+
+
 @dataclass(frozen=True)
 class PlanInfo:
     n_rows: int
@@ -321,10 +347,16 @@ class Plan:
         torch = self._torch()
         need = self.workspace_bytes(batch)
         if ws is not None:
-            return ws
+            return expect_workspace(ws, device)
         if self._ws is None or self._ws.numel() < need or self._ws.device != device:
             self._ws = torch.empty(need, dtype=torch.uint8, device=device)
         return self._ws
+
+    def _out(self, out, shape, dtype, device, what="out"):
+        """A new output tensor, or the caller's after checking it exactly."""
+        if out is None:
+            return self._torch().empty(shape, dtype=dtype, device=device)
+        return expect_tensor(out, shape, dtype, device, what)
 
     def _call(self, fn, what, src, dst, batch, ws, stream):
         torch = self._torch()
@@ -359,8 +391,7 @@ class Plan:
         x = self._check_signal(x)
         lead = x.shape[:-1]
         batch = int(np.prod(lead)) if len(lead) else 1
-        y = out if out is not None else torch.empty(tuple(lead) + (self.R, self.N_out),
-                                                    dtype=self._complex_dtype(), device=x.device)
+        y = self._out(out, tuple(lead) + (self.R, self.N_out), self._complex_dtype(), x.device)
         self._call(lib.qtam_forward, "qtam_forward", x, y, batch, ws, stream)
         return y
 
@@ -371,10 +402,8 @@ class Plan:
         x = self._check_signal(x)
         lead = x.shape[:-1]
         batch = int(np.prod(lead)) if len(lead) else 1
-        y = out if out is not None else torch.empty(tuple(lead) + (self.R, self.N_out),
-                                                    dtype=self._complex_dtype(), device=x.device)
-        m = metric if metric is not None else torch.empty(tuple(lead) + (self.R,), dtype=self._complex_dtype(),
-                                                          device=x.device)
+        y = self._out(out, tuple(lead) + (self.R, self.N_out), self._complex_dtype(), x.device)
+        m = self._out(metric, tuple(lead) + (self.R,), self._complex_dtype(), x.device, "metric")
         if stream is None:
             stream = torch.cuda.current_stream(x.device)
         ws = self._workspace(batch, x.device, ws)
@@ -392,8 +421,7 @@ class Plan:
         y = self._check_rows(y)
         lead = y.shape[:-2]
         batch = int(np.prod(lead)) if len(lead) else 1
-        x = out if out is not None else torch.empty(tuple(lead) + (self.N,), dtype=self._real_dtype(),
-                                                    device=y.device)
+        x = self._out(out, tuple(lead) + (self.N,), self._real_dtype(), y.device)
         if stream is None:
             stream = torch.cuda.current_stream(y.device)
         ws = self._workspace(batch, y.device, ws)
@@ -410,8 +438,7 @@ class Plan:
         y = self._check_rows(y)
         lead = y.shape[:-2]
         batch = int(np.prod(lead)) if len(lead) else 1
-        d = out if out is not None else torch.empty(tuple(lead) + (self.R, self.N), dtype=self._complex_dtype(),
-                                                    device=y.device)
+        d = self._out(out, tuple(lead) + (self.R, self.N), self._complex_dtype(), y.device)
         if batch == 0:
             return d
         need = int(lib.qtam_dense_workspace_size(self._h, batch))
@@ -419,6 +446,8 @@ class Plan:
             raise QtamError(QTAM_ERR_UNSUPPORTED, "qtam_dense")
         if ws is None:
             ws = torch.empty(need, dtype=torch.uint8, device=y.device)
+        else:
+            expect_workspace(ws, y.device)
         if stream is None:
             stream = torch.cuda.current_stream(y.device)
         _check(lib.qtam_dense(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(d.data_ptr()), int(batch),
@@ -455,8 +484,7 @@ class Plan:
         y = self._check_rows(y)
         lead = y.shape[:-2]
         batch = int(np.prod(lead)) if len(lead) else 1
-        x = out if out is not None else torch.empty(tuple(lead) + (self.N,), dtype=self._real_dtype(),
-                                                    device=y.device)
+        x = self._out(out, tuple(lead) + (self.N,), self._real_dtype(), y.device)
         self._call(lib.qtam_inverse, "qtam_inverse", y, x, batch, ws, stream)
         return x
 
@@ -465,8 +493,7 @@ class Plan:
         gy = self._check_rows(gy)
         lead = gy.shape[:-2]
         batch = int(np.prod(lead)) if len(lead) else 1
-        gx = out if out is not None else torch.empty(tuple(lead) + (self.N,), dtype=self._real_dtype(),
-                                                     device=gy.device)
+        gx = self._out(out, tuple(lead) + (self.N,), self._real_dtype(), gy.device)
         self._call(lib.qtam_forward_adjoint, "qtam_forward_adjoint", gy, gx, batch, ws, stream)
         return gx
 
@@ -475,8 +502,7 @@ class Plan:
         gx = self._check_signal(gx)
         lead = gx.shape[:-1]
         batch = int(np.prod(lead)) if len(lead) else 1
-        gy = out if out is not None else torch.empty(tuple(lead) + (self.R, self.N_out),
-                                                     dtype=self._complex_dtype(), device=gx.device)
+        gy = self._out(out, tuple(lead) + (self.R, self.N_out), self._complex_dtype(), gx.device)
         self._call(lib.qtam_inverse_adjoint, "qtam_inverse_adjoint", gx, gy, batch, ws, stream)
         return gy
 
@@ -512,16 +538,15 @@ def forward_sweep(plans, x, outs=None, ws=None, stream=None):
     outs = list(outs)
     if len(outs) != len(plans):
         raise ValueError("one output per plan")
-    for p, y in zip(plans, outs):
-        if (y.dtype != p._complex_dtype() or tuple(y.shape) != tuple(lead) + (p.R, p.N_out)
-                or not y.is_contiguous() or y.device != x.device):
-            raise ValueError("output of plan with R=%d, N_out=%d must be a contiguous %s %s on %s" % (
-                p.R, p.N_out, p._complex_dtype(), tuple(lead) + (p.R, p.N_out), x.device))
+    for i, (p, y) in enumerate(zip(plans, outs)):
+        expect_tensor(y, tuple(lead) + (p.R, p.N_out), p._complex_dtype(), x.device, "output %d" % i)
     if stream is None:
         stream = torch.cuda.current_stream(x.device)
     if ws is None:
         need = max(p.workspace_bytes(batch) for p in plans)
         ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    else:
+        expect_workspace(ws, x.device)
     n = len(plans)
     hs = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
     ys = (ctypes.c_void_p * n)(*[y.data_ptr() for y in outs])

@@ -251,3 +251,34 @@ def test_unknown_precision_rejected():
         host_plan(sample_rate=1024.0, n_samples=4096, q=8.0, f_min=10.0, f_max=400.0, n_rows=16, precision="fp16")
     assert host_plan(sample_rate=1024.0, n_samples=4096, q=8.0, f_min=10.0, f_max=400.0, n_rows=16,
                      precision="float64").fp64
+
+
+def test_output_and_workspace_checks():
+    """Caller-supplied outputs and workspaces are checked for exact shape,
+    dtype, device and contiguity before any pointer reaches the library (it
+    writes the whole expected shape through the base pointer)."""
+    import torch
+    dev = torch.device("cpu")
+    good = torch.empty((2, 3, 8), dtype=torch.complex64)
+    assert binding.expect_tensor(good, (2, 3, 8), torch.complex64, dev, "out") is good
+    bad = [
+        torch.empty((2, 3, 7), dtype=torch.complex64),             # short rows
+        torch.empty((1, 3, 8), dtype=torch.complex64),             # short batch
+        torch.empty((2, 3, 8), dtype=torch.complex128),            # dtype
+        torch.empty((2, 8, 3), dtype=torch.complex64).transpose(1, 2),   # strided
+        torch.empty((2, 3, 16), dtype=torch.complex64)[..., ::2],  # strided view
+        np.zeros((2, 3, 8), dtype=np.complex64),                   # not a tensor
+    ]
+    for t in bad:
+        with pytest.raises(ValueError):
+            binding.expect_tensor(t, (2, 3, 8), torch.complex64, dev, "out")
+    with pytest.raises(ValueError):
+        binding.expect_tensor(good, (2, 3, 8), torch.complex64, torch.device("cuda", 0), "out")
+    ws = torch.empty(1024, dtype=torch.uint8)
+    assert binding.expect_workspace(ws, dev) is ws
+    with pytest.raises(ValueError):
+        binding.expect_workspace(ws, torch.device("cuda", 0))
+    with pytest.raises(ValueError):
+        binding.expect_workspace(torch.empty(2048, dtype=torch.uint8)[::2], dev)
+    with pytest.raises(ValueError):
+        binding.expect_workspace(bytearray(16), dev)
