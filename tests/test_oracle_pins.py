@@ -166,15 +166,52 @@ def test_geometric_grid_and_floor():
 
 
 def test_paper_printed_sizes():
-    """Sizes printed in the paper (Sec. IV results; App. B) and what they fix."""
+    """Sizes the paper prints (App. B: 62 x 12289 standard and 62 x 669
+    minimal outputs of 6 s segments at 4096 Hz; Sec. IV: a 64 x 410 dense
+    tile of 0.2 s at 4096 Hz) against the oracle's own plans and outputs.
+
+    * The standard width is the one-sided spectrum of the segment: the
+      oracle's spectrum of a 24576-sample segment has 12289 bins, and a
+      62-row plan has 62 rows.
+    * The minimal width n = ceil(N_t df_max) + 1 (App. A) is lossless: under
+      the printed cap the oracle's widest support fits in n, n itself is an
+      accepted output length whose round trip returns the projection x_M to
+      machine precision (P1), and an output shorter than the widest support
+      is rejected. The paper gives no frequency range for its glitch tensor;
+      the 10-2048 Hz band is a reading, so the printed 669 itself stays
+      unpinned and only the formula is checked.
+    * 0.2 s at 4096 Hz is 819.2 samples; with the even length 818 the
+      oracle's one-sided spectrum has the printed 410 bins."""
     with open(os.path.join(GOLDEN, "paper_printed.json")) as fh:
         g = json.load(fh)
     std = g["standard_output_6s"]
-    # standard output length = one-sided spectrum length of the segment
-    assert std["cols"] == std["n_samples"] // 2 + 1
+    fs, n, rows = float(std["fs"]), int(std["n_samples"]), int(std["rows"])
+    T = n / fs
+    kw = dict(fs=fs, n=n, q=8.0, f_min=10.0, f_max=fs / 2, rows=rows)
+    paper = o.OraclePlan(cap_mode=o.CAP_PAPER, **kw)
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal(n)
+    X = paper.spectrum(x)
+    assert paper.R == rows and X.shape == (std["cols"],) and paper.n_bins == std["cols"]
+    assert np.abs(X - np.fft.rfft(x)).max() <= 1e-9 * np.abs(X).max()
+    f = paper.row_table()["freq"]
+    gap = int(math.ceil(T * float(np.max(np.diff(f)))))
+    n_min = gap + 1
+    assert paper.l_max == 2 * (gap // 2) + 1
+    assert paper.max_len <= n_min
+    minimal = o.OraclePlan(cap_mode=o.CAP_PAPER, n_out=n_min, **kw)
+    assert minimal.N_out == n_min
+    Y = minimal.forward(x)
+    assert Y.shape == (rows, n_min)
+    xm = minimal.project(x)
+    assert np.linalg.norm(minimal.inverse(Y) - xm) <= 1e-12 * np.linalg.norm(xm)
+    with pytest.raises(ValueError):
+        o.OraclePlan(cap_mode=o.CAP_PAPER, n_out=paper.max_len - 1, **kw)
     gw = g["gw150914_demo"]
-    assert gw["cols_dense"] == int(gw["duration_s"] * gw["fs"]) // 2 + 1
-    assert gw["cols_dense"] / gw["cols_demod"] == pytest.approx(gw["compression"], rel=0.05)
+    n_gw = int(gw["duration_s"] * gw["fs"]) // 2 * 2
+    demo = o.OraclePlan(fs=float(gw["fs"]), n=n_gw, q=8.0, f_min=30.0, f_max=500.0, rows=gw["rows"])
+    assert demo.n_bins == gw["cols_dense"] and demo.spectrum(rng.standard_normal(n_gw)).shape == (gw["cols_dense"],)
+    assert demo.R == gw["rows"]
 
 
 # --------------------------------------------------------------------------
