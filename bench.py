@@ -109,8 +109,43 @@ def measured_traffic(kernel: str, batch: int):
     return float(kv[kernel])
 
 
-def kernel_bytes(kind: str, plan, batch: int, b: int) -> float:
-    """Algorithmic bytes one launch of a kernel must move (b = bytes per real)."""
+def long_rows(plan) -> bool:
+    """Envelope rows longer than one workgroup's transform go through two
+    passes (the first forward pass and the second inverse pass then move only
+    the intermediate)."""
+    return plan.N_out > (8192 if plan.fp64 else 32768)
+
+
+def kernel_bytes(kind: str, plan, batch: int, b: int):
+    """Algorithmic bytes of one launch (b = bytes per real): the kernel's share
+    of what forward + inverse must move per segment, 2 b N + 4 b R N_out (read
+    the signal, write the envelopes, read them, write the reconstruction).
+    Kernels that only pass intermediates between those (spectrum, packed kept
+    slots, half spectrum) have a share of 0."""
+    N, R, no = plan.N, plan.R, plan.N_out
+    x, y = N * b, R * no * 2 * b
+    two = long_rows(plan)
+    # N/2 = 3 2^k or 5 2^k: a permutation kernel reads the signal and another
+    # writes the reconstruction; the power-of-two transforms between move
+    # intermediates only
+    dec = (N // 2) & (N // 2 - 1) != 0
+    xt = 0 if dec else x
+    per_seg = {
+        "spectrum_fft": xt, "spectrum_fft_pass1": xt, "spectrum_permute": x,    # read the signal
+        "spectrum_fft_pass2": 0, "spectrum_twist": 0, "spectrum_radix": 0,
+        "fwd_rows": 0 if two else y, "fwd_rows_pass2": y if two else 0,        # write the envelopes
+        "inv_rows": y, "inv_rows_pass2": 0,                                     # read the envelopes
+        "overlap_add": 0, "synthesis_radix": 0, "synthesis_fft_pass1": 0,
+        "synthesis_fft": xt, "synthesis_fft_pass2": xt, "synthesis_permute": x,  # write the reconstruction
+    }.get(kind)
+    return None if per_seg is None else float(per_seg) * batch
+
+
+def design_bytes(kind: str, plan, batch: int, b: int):
+    """Bytes one launch reads and writes once by this design (its input and
+    output buffers, intermediates included): signal [N], half spectrum [N/2]
+    complex, envelopes [R, N_out] complex, kept slots [sum of row supports]
+    complex, per segment."""
     N, R, no, sl = plan.N, plan.R, plan.N_out, plan.info.sum_len
     c = 2 * b
     per_seg = {
@@ -126,6 +161,18 @@ def kernel_bytes(kind: str, plan, batch: int, b: int) -> float:
         "synthesis_fft_pass2": (N // 2) * c + N * b,
     }.get(kind)
     return None if per_seg is None else float(per_seg) * batch
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), else the platform's."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def main():
@@ -237,15 +284,17 @@ def main():
         torch.cuda.synchronize()
         for p in plans:
             for name, (ms, cnt) in p.timing_collect().items():
-                k = kernels.setdefault(name, dict(total_ms=0.0, launches=0, bytes=0.0))
+                k = kernels.setdefault(name, dict(total_ms=0.0, launches=0, bytes=0.0, design_bytes=0.0))
                 k["total_ms"] += ms
                 k["launches"] += cnt
-                kb = kernel_bytes(name, p, B, b)
-                k["bytes"] += (kb or 0.0) * reps   # one call per plan and step covers the batch (in chunks)
+                # one call per plan and step covers the batch (in chunks)
+                k["bytes"] += (kernel_bytes(name, p, B, b) or 0.0) * reps
+                k["design_bytes"] += (design_bytes(name, p, B, b) or 0.0) * reps
             p.timing(False)
         for name, k in kernels.items():
             k["avg_ms"] = k["total_ms"] / max(k["launches"], 1)
             k["achieved_GBs"] = k["bytes"] / (k["total_ms"] * 1e-3) / 1e9 if k["total_ms"] > 0 else None
+            k["design_GBs"] = k["design_bytes"] / (k["total_ms"] * 1e-3) / 1e9 if k["total_ms"] > 0 else None
         # whole path by the calibrated HBM counters of the committed profile
         # (when it was taken on these kernel sources): bytes moved per step
         # over the step time
@@ -261,11 +310,17 @@ def main():
         dom = max(kernels, key=lambda n: kernels[n]["total_ms"])
         k = kernels[dom]
         ach = k["achieved_GBs"]
+        nl = max(k["launches"], 1)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(dom, B) if args.precision == "fp32" else None,
                     "avg_launch_ms": round(k["avg_ms"], 4),
-                    "bytes_per_launch": k["bytes"] / max(k["launches"], 1)}
+                    "bytes_per_launch": k["bytes"] / nl,
+                    "bytes_what": "the kernel's share of the algorithmic bytes 2bN + 4bR N_out per segment "
+                                  "and plan (read x, write Y, read Y, write x-hat), x segments per launch",
+                    "design_bytes_per_launch": k["design_bytes"] / nl,
+                    "design_frac": round(k["design_GBs"] / HBM_PEAK_GBS, 4),
+                    "design_what": "every buffer the kernel reads or writes once, intermediates included"}
 
     out = {
         "metric": "fwd+inv QTAM samples/s @1 GPU; p50/p99 latency; recon rel-err vs FP64",
@@ -477,7 +532,7 @@ def cpu_all_cores_leg(W, prec, cores, seconds):
         out = [f.result(timeout=4 * seconds + 120) for f in futs]
     done = sum(d for d, _ in out)
     rate = sum(d * W["n"] / t for d, t in out)   # processes ran concurrently: rates add
-    return {"value": rate, "unit": "samples/s", "cores": cores, "kind": "oracle",
+    return {"value": rate, "unit": "samples/s", "cores": cores, "kind": "oracle", "host": cpu_model(),
             "sample": "%d segments of %d samples over %d processes (one per core, plans cycling Q=4/8/16), "
                       "FP64 forward+inverse, %.0f s each" % (done, W["n"], cores, seconds)}
 
@@ -523,7 +578,7 @@ def cpu_leg(args, plans, x_host, x_dev, B, W):
     cpu = {"value": cpu_value, "unit": "samples/s", "cores": 1, "kind": "oracle",
            "sample": "%d segments of %d samples (plans cycling Q=4/8/16), FP64 forward+inverse, "
                      "single thread, %.1f s of oracle time" % (done, W["n"], t_oracle),
-           "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+           "host": cpu_model(), "host_cpus": os.cpu_count()}
     res = {"cpu_baseline": cpu,
            "recon_rel_err": {"coef_max": max(errs_y), "recon_max": max(errs_x), "segments": done,
                              "vs": "FP64 CPU oracle", "precision": prec}}
