@@ -193,8 +193,9 @@ qtam_status qtam_tile_inverse(qtam_plan_t plan, const void* y, int32_t row, void
  *   T_k[tau] = (1/N) sum_b X[b] W_k[b] e^{+2 pi i b tau / N},  tau = 0..N-1,
  * from the envelopes y [batch, R, N_out] (each row re-modulated to its
  * carrier and band-limited up-sampled to N samples; this is the dense row the
- * forward transform decimates). Needs N a power of two (else
- * QTAM_ERR_UNSUPPORTED) and the workspace qtam_dense_workspace_size gives
+ * forward transform decimates). Needs N = r * 2^k with r in {1, 3, 5}, as
+ * the plan's spectrum does (the paper's 6 s x 4096 Hz segment is 3 * 8192),
+ * else QTAM_ERR_UNSUPPORTED, and the workspace qtam_dense_workspace_size gives
  * (0 when the plan has no dense path); one segment's tiles must stay below
  * 2 GiB. Smaller workspaces that hold one segment are used in chunks.       */
 size_t qtam_dense_workspace_size(qtam_plan_t plan, int64_t batch);

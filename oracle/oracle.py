@@ -63,6 +63,8 @@ def lib():
         L.ora_dft.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_int32]
         for name in ("ora_spectrum", "ora_forward", "ora_inverse", "ora_synthesis"):
             getattr(L, name).argtypes = [ctypes.c_void_p, dp, ctypes.c_int64, dp]
+        L.ora_forward_rows.argtypes = [ctypes.c_void_p, dp, ctypes.c_int64, i64p, ctypes.c_int64, dp]
+        L.ora_forward_rows.restype = ctypes.c_int
         L.ora_dense.argtypes = [ctypes.c_void_p, dp, dp]
         L.ora_tile_inverse.argtypes = [ctypes.c_void_p, dp, ctypes.c_int32, ctypes.c_int64, dp]
         L.ora_tile_inverse.restype = ctypes.c_int
@@ -177,6 +179,17 @@ class OraclePlan:
         x2, one = self._signal(x)
         Y = np.zeros((x2.shape[0], self.R, self.N_out), dtype=np.complex128)
         lib().ora_forward(self._h, _dp(x2), x2.shape[0], _dp(Y.view(np.float64)))
+        return Y[0] if one else Y
+
+    def forward_rows(self, x, rows):
+        """Coefficients of the given rows only, shape [batch, len(rows), N_out]
+        (or [len(rows), N_out] for one segment)."""
+        x2, one = self._signal(x)
+        idx = np.ascontiguousarray(rows, dtype=np.int64)
+        Y = np.zeros((x2.shape[0], idx.size, self.N_out), dtype=np.complex128)
+        if lib().ora_forward_rows(self._h, _dp(x2), x2.shape[0], idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  idx.size, _dp(Y.view(np.float64))) != 0:
+            raise IndexError("row index out of range")
         return Y[0] if one else Y
 
     def inverse(self, Y):

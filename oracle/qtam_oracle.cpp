@@ -407,20 +407,27 @@ int64_t wrap(int64_t j, int64_t m) {
 // to slot 0, offset j to slot j mod N_out), zero-pad to N_out and take the
 // short inverse DFT with the renormalisation sqrt(N_out/N) (Sec. III; App. A;
 // App. C, demodulation equations; N_in read as N).
-void forward_one(const Plan& pl, const double* x, cd* Y) {
+// Rows idx[0..count) of the segment, in that order (every row: idx = 0..R-1).
+void forward_rows(const Plan& pl, const double* x, const int64_t* idx, int64_t count, cd* Y) {
   std::vector<cd> X;
   spectrum(pl, x, X);
   const int64_t m = pl.n_out;
   const double norm = std::sqrt(static_cast<double>(m) / static_cast<double>(pl.n)) / static_cast<double>(m);
   std::vector<cd> Z(static_cast<size_t>(m)), y(static_cast<size_t>(m));
-  for (size_t k = 0; k < pl.rows.size(); ++k) {
-    const Row& r = pl.rows[k];
+  for (int64_t i = 0; i < count; ++i) {
+    const Row& r = pl.rows[static_cast<size_t>(idx[i])];
     std::fill(Z.begin(), Z.end(), cd(0.0, 0.0));
     for (int64_t c = r.lo; c <= r.hi; ++c)
       Z[static_cast<size_t>(wrap(c - r.s, m))] += X[static_cast<size_t>(c)] * r.w[static_cast<size_t>(c - r.lo)];
     dft(m, Z.data(), y.data(), +1);
-    for (int64_t t = 0; t < m; ++t) Y[static_cast<int64_t>(k) * m + t] = y[static_cast<size_t>(t)] * norm;
+    for (int64_t t = 0; t < m; ++t) Y[i * m + t] = y[static_cast<size_t>(t)] * norm;
   }
+}
+
+void forward_one(const Plan& pl, const double* x, cd* Y) {
+  std::vector<int64_t> all(pl.rows.size());
+  for (size_t k = 0; k < all.size(); ++k) all[k] = static_cast<int64_t>(k);
+  forward_rows(pl, x, all.data(), static_cast<int64_t>(all.size()), Y);
 }
 
 // O10-O12 inverse, one segment: DFT each row, re-modulate it to its carrier
@@ -568,6 +575,18 @@ void ora_forward(void* h, const double* x, int64_t batch, double* Y) {
   const int64_t per = static_cast<int64_t>(pl.rows.size()) * pl.n_out;
   for (int64_t b = 0; b < batch; ++b)
     forward_one(pl, x + b * pl.n, reinterpret_cast<cd*>(Y) + b * per);
+}
+
+// Forward coefficients of the rows idx[0..count) only (sampled rows of
+// plans too large for every row): Y [batch, count, N_out]. Returns 1 if an
+// index is out of range.
+int ora_forward_rows(void* h, const double* x, int64_t batch, const int64_t* idx, int64_t count, double* Y) {
+  const Plan& pl = *static_cast<Plan*>(h);
+  for (int64_t i = 0; i < count; ++i)
+    if (idx[i] < 0 || idx[i] >= static_cast<int64_t>(pl.rows.size())) return 1;
+  for (int64_t b = 0; b < batch; ++b)
+    forward_rows(pl, x + b * pl.n, idx, count, reinterpret_cast<cd*>(Y) + b * count * pl.n_out);
+  return 0;
 }
 
 void ora_inverse(void* h, const double* Y, int64_t batch, double* x) {

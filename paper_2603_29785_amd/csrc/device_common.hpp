@@ -16,6 +16,26 @@ struct RowMeta {
   int s, lo, hi, off;   // centre bin, kept bin range, offset in the packed tables
 };
 
+// Envelope slot u of a row holds the kept bin c with (c - s) mod L = u (the
+// roll of bin s to slot 0, Sec. III / App. A). The support holds at most L
+// bins, so that bin is unique when it exists: c = lo + d with
+// d = (u + s - lo) mod L, kept iff d <= hi - lo. Slot entries of a
+// power-of-two L:
+template <int L>
+__device__ __forceinline__ int slot_entry(int u, const RowMeta& rm) {
+  static_assert((L & (L - 1)) == 0, "power-of-two rows");
+  return (u + rm.s - rm.lo) & (L - 1);
+}
+
+// A row is centred when its support lies inside s - L/2 .. s + L/2 - 1: the
+// signed slot offset j (u, or u - L above L/2) then gives c = s + j directly.
+// Every row whose window is narrower than the band is centred (its support
+// is within s - h .. s + h and 2h + 1 <= L); a row of a regularised window
+// keeps the whole band 0..N/2 and may not be.
+__device__ __forceinline__ bool row_centred(const RowMeta& rm, int L) {
+  return rm.lo >= rm.s - L / 2 && rm.hi < rm.s + L / 2;
+}
+
 // exp(-2 pi i m / N) for m in [0, N) as fine[m & (F-1)] * coarse[m >> log2 F]
 template <typename C>
 struct Twiddle2 {

@@ -50,14 +50,15 @@ namespace {
 
 enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_TWIST, K_FWD_ROWS, K_FWD_ROWS2, K_INV_ROWS, K_INV_ROWS2, K_OLA,
             K_SYN, K_SYN1, K_SYN2, K_ROW_STATS, K_PLANE_BEST, K_GATHER, K_SPEC_PERM, K_SPEC_RADIX, K_SYN_RADIX,
-            K_SYN_PERM, K_DENSE_PLACE, K_DENSE_FFT, K_DENSE_FFT1, K_DENSE_FFT2, K_NUM };
+            K_SYN_PERM, K_DENSE_PLACE, K_DENSE_FFT, K_DENSE_FFT1, K_DENSE_FFT2, K_DENSE_RADIX, K_DENSE_PERM,
+            K_NUM };
 const char* const kKindName[K_NUM] = {"spectrum_fft", "spectrum_fft_pass1", "spectrum_fft_pass2",
                                        "spectrum_twist", "fwd_rows", "fwd_rows_pass2", "inv_rows",
                                        "inv_rows_pass2", "overlap_add", "synthesis_fft",
                                        "synthesis_fft_pass1", "synthesis_fft_pass2", "row_stats",
                                        "plane_best", "gather_plane", "spectrum_permute", "spectrum_radix",
                                        "synthesis_radix", "synthesis_permute", "dense_place", "dense_fft",
-                                       "dense_fft_pass1", "dense_fft_pass2"};
+                                       "dense_fft_pass1", "dense_fft_pass2", "dense_radix", "dense_permute"};
 
 enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3, T_DENSE = 4, T_TILE = 5 };
 
@@ -113,10 +114,11 @@ struct qtam_plan_s {
   int tw2_bits = 0;
   bool four_step = false;       // the length-M2 transforms run as two passes
   int64_t n1 = 0, n2 = 0;       // M2 = n1 * n2 when four_step
-  bool dense_ok = false;        // N a power of two: dense tiles available
-  bool dense_four_step = false; // N-point dense transforms in two passes, N = dn1 * dn2
+  bool dense_ok = false;        // dense tiles available
+  int64_t dense_md = 0;         // N = radix_r * dense_md: power-of-two part of the N-point transforms
+  bool dense_four_step = false; // dense_md-point transforms in two passes, dense_md = dn1 * dn2
   int64_t dn1 = 0, dn2 = 0;
-  void* d_tw_dense = nullptr;   // Stockham twiddles of N (single pass)
+  void* d_tw_dense = nullptr;   // Stockham twiddles of dense_md (single pass)
   void* d_tw_dn1 = nullptr;
   void* d_tw_dn2 = nullptr;
   bool bluestein = false;       // N_out not a power of two: chirp-z rows of length bs_len
@@ -128,7 +130,9 @@ struct qtam_plan_s {
   int radix_r = 1;              // N/2 = radix_r * m2
   int64_t m2 = 0;               // power-of-two transform length of the spectrum
   bool big_rows = false;        // N_out beyond one workgroup: four-step rows through the workspace
-  int64_t r1 = 0, r2 = 0;       // N_out = r1 * r2
+  bool bs_long = false;         // chirp-z rows whose bs_len exceeds one workgroup: element passes
+                                // around four-step transforms through the workspace
+  int64_t r1 = 0, r2 = 0;       // N_out = r1 * r2 (big_rows), bs_len = r1 * r2 (bs_long)
   void* d_tw_r1 = nullptr;
   void* d_tw_r2 = nullptr;
   void* d_twr_fine = nullptr;   // two-level exp(-2 pi i m / N_out)
@@ -302,17 +306,18 @@ qtam_status upload(qtam_plan_s* pl) {
     o_n2 = blob.add(tw.data(), tw.size() * sizeof(T));
   }
   size_t o_r1 = 0, o_r2 = 0, o_rf = 0, o_rc = 0;
-  if (pl->big_rows) {
+  if (pl->big_rows || pl->bs_long) {
+    const int64_t lr = pl->big_rows ? int64_t(hp.n_out) : pl->bs_len;   // r1 * r2
     stockham_twiddles(tw, pl->r1, engine_e(pl->r1, f64), TW_POW);
     o_r1 = blob.add(tw.data(), tw.size() * sizeof(T));
     stockham_twiddles(tw, pl->r2, engine_e(pl->r2, f64), TW_POW);
     o_r2 = blob.add(tw.data(), tw.size() * sizeof(T));
-    const int nbr = ilog2(hp.n_out);
+    const int nbr = ilog2(lr);
     pl->twr_bits = (nbr + 1) / 2;
-    const int64_t nf = int64_t(1) << pl->twr_bits, ncs = int64_t(hp.n_out) >> pl->twr_bits;
-    twiddles_strided(tw, nf, 1, hp.n_out);
+    const int64_t nf = int64_t(1) << pl->twr_bits, ncs = lr >> pl->twr_bits;
+    twiddles_strided(tw, nf, 1, lr);
     o_rf = blob.add(tw.data(), tw.size() * sizeof(T));
-    twiddles_strided(tw, ncs, nf, hp.n_out);
+    twiddles_strided(tw, ncs, nf, lr);
     o_rc = blob.add(tw.data(), tw.size() * sizeof(T));
   }
   size_t o_bsc = 0, o_bsf = 0, o_bsi = 0, o_bstw = 0;
@@ -347,13 +352,15 @@ qtam_status upload(qtam_plan_s* pl) {
     o_bsc = blob.add(ta.data(), ta.size() * sizeof(T));
     o_bsf = blob.add(tf.data(), tf.size() * sizeof(T));
     o_bsi = blob.add(ti.data(), ti.size() * sizeof(T));
-    stockham_twiddles(tw, Lb, engine_e(Lb, f64), TW_POW);
-    o_bstw = blob.add(tw.data(), tw.size() * sizeof(T));
+    if (!pl->bs_long) {   // one-workgroup rows: Stockham twiddles of the whole length
+      stockham_twiddles(tw, Lb, engine_e(Lb, f64), TW_POW);
+      o_bstw = blob.add(tw.data(), tw.size() * sizeof(T));
+    }
   }
   size_t o_dt = 0, o_dn1 = 0, o_dn2 = 0;
   if (pl->dense_ok) {
     if (!pl->dense_four_step) {
-      stockham_twiddles(tw, hp.n, engine_e(hp.n, f64), TW_POW);
+      stockham_twiddles(tw, pl->dense_md, engine_e(pl->dense_md, f64), TW_POW);
       o_dt = blob.add(tw.data(), tw.size() * sizeof(T));
     } else {
       stockham_twiddles(tw, pl->dn1, engine_e(pl->dn1, f64), TW_POW);
@@ -396,12 +403,12 @@ qtam_status upload(qtam_plan_s* pl) {
     pl->d_bs_chirp = d + o_bsc;
     pl->d_bs_bf = d + o_bsf;
     pl->d_bs_bi = d + o_bsi;
-    pl->d_bs_tw = d + o_bstw;
+    pl->d_bs_tw = pl->bs_long ? nullptr : d + o_bstw;
   }
   pl->d_tw_half = pl->four_step ? nullptr : d + o_half;
   pl->d_tw_n1 = pl->four_step ? d + o_n1 : nullptr;
   pl->d_tw_n2 = pl->four_step ? d + o_n2 : nullptr;
-  if (pl->big_rows) {
+  if (pl->big_rows || pl->bs_long) {
     pl->d_tw_r1 = d + o_r1;
     pl->d_tw_r2 = d + o_r2;
     pl->d_twr_fine = d + o_rf;
@@ -672,6 +679,7 @@ WsLayout layout_for(const qtam_plan_s* pl, int64_t segs) {
   off = align256(off + size_t(segs) * size_t(pl->hp.sum_len) * cb);
   w.rows = off;
   if (pl->big_rows) off = align256(off + size_t(segs) * size_t(pl->hp.rows) * size_t(pl->hp.n_out) * cb);
+  if (pl->bs_long) off = align256(off + 2 * size_t(segs) * size_t(pl->hp.rows) * size_t(pl->bs_len) * cb);
   w.total = off;
   return w;
 }
@@ -685,7 +693,7 @@ int64_t chunk_cap(const qtam_plan_s* pl) {
                                size_t(hp.sum_len) * 2 * rb});
   const size_t lim = size_t(1) << 31;
   int64_t cap = per > lim ? 0 : int64_t(lim / per);
-  if (pl->big_rows) cap = std::min<int64_t>(cap, 65535 / hp.rows);   // rows of a chunk index grid.y
+  if (pl->big_rows || pl->bs_long) cap = std::min<int64_t>(cap, 65535 / hp.rows);   // rows of a chunk index grid.y
   cap = std::min<int64_t>(cap, 65535 / pl->radix_r);                  // decimated rows index grid.y
   return cap;
 }
@@ -800,6 +808,48 @@ bool analysis_spectrum(qtam_plan_s* pl, const void* x, int64_t segs, char* ws, c
   return true;
 }
 
+// Chirp-z rows beyond one workgroup, for one chunk: the length-L cyclic
+// convolution of each row (L = bs_len = r1 * r2) as a forward and an inverse
+// four-step transform through two workspace buffers A and B of
+// segs * R * L values (ws + lay.rows), between element passes:
+//   forward:  prep (gather x table x chirp) -> B, FFT B -> B (via A),
+//             B *= Bhat_f, IFFT B -> B (via A), y = B x chirp;
+//   inverse:  prep (y x conj chirp) -> B, FFT, B *= Bhat_i, IFFT,
+//             kept slots x conj chirp x table -> packed.
+template <typename T>
+bool chirp_rows_long(qtam_plan_s* pl, bool forward, int table, const void* in, void* out, int64_t segs, char* ws,
+                     const WsLayout& lay, hipStream_t st) {
+  using C = typename Complex<T>::type;
+  const HostPlan& hp = pl->hp;
+  const int64_t L = pl->bs_len, count = segs * hp.rows;
+  const int M = hp.n_out;
+  C* A = reinterpret_cast<C*>(ws + lay.rows);
+  C* B = A + count * L;
+  const Twiddle2<C> twr{static_cast<const C*>(pl->d_twr_fine), static_cast<const C*>(pl->d_twr_coarse),
+                        pl->twr_bits};
+  const C* chirp = static_cast<const C*>(pl->d_bs_chirp);
+  const dim3 gl(unsigned((L + 255) / 256), unsigned(count)), gm(unsigned((M + 255) / 256), unsigned(count));
+  if (forward)
+    hipLaunchKernelGGL((k_bs_fwd_prep<T>), gl, dim3(256), 0, st, static_cast<const C*>(in), B, pl->d_rows,
+                       static_cast<const T*>(pl->d_tab[table]), hp.rows, int(hp.half), M, L, chirp);
+  else
+    hipLaunchKernelGGL((k_bs_inv_prep<T>), gl, dim3(256), 0, st, static_cast<const C*>(in), B, M, L, chirp);
+  if (!launch_fft_cols<T, -1>(ilog2(pl->r2), B, A, pl->r1, count, L, pl->d_tw_r2, twr, st, 1) ||
+      !launch_fft_rows_t<T, -1>(ilog2(pl->r1), A, B, pl->r2, count, L, pl->d_tw_r1, st))
+    return false;
+  hipLaunchKernelGGL((k_bs_mul<T>), gl, dim3(256), 0, st, B, L,
+                     static_cast<const C*>(forward ? pl->d_bs_bf : pl->d_bs_bi));
+  if (!launch_fft_cols<T, +1>(ilog2(pl->r2), B, A, pl->r1, count, L, pl->d_tw_r2, twr, st, 1) ||
+      !launch_fft_rows_t<T, +1>(ilog2(pl->r1), A, B, pl->r2, count, L, pl->d_tw_r1, st))
+    return false;
+  if (forward)
+    hipLaunchKernelGGL((k_bs_fwd_post<T>), gm, dim3(256), 0, st, B, static_cast<C*>(out), M, L, chirp);
+  else
+    hipLaunchKernelGGL((k_bs_inv_post<T>), gm, dim3(256), 0, st, B, static_cast<C*>(out), pl->d_rows,
+                       static_cast<const T*>(pl->d_tab[table]), hp.rows, int64_t(hp.sum_len), M, L, chirp);
+  return true;
+}
+
 // analysis, second half: spectrum -> rows (forward with T_FWD, inverse adjoint
 // with T_AINV). Reads ws + lay.spec, writes y (and ws + lay.rows for long rows).
 template <typename T>
@@ -833,7 +883,10 @@ bool analysis_rows(qtam_plan_s* pl, int table, void* y, int64_t segs, char* ws, 
   }
   if (pl->bluestein) {
     using C = typename Complex<T>::type;
-    {
+    if (pl->bs_long) {
+      Timed tm(pl, K_FWD_ROWS, st);
+      if (!chirp_rows_long<T>(pl, true, table, spec, y, segs, ws, lay, st)) return false;
+    } else {
       Timed tm(pl, K_FWD_ROWS, st);
       if (!launch_rows_bs<T>(true, ilog2(pl->bs_len), spec, y, pl->d_rows, pl->d_tab[table], hp.rows, segs * hp.rows,
                              half, hp.sum_len, hp.n_out, pl->d_bs_chirp, pl->d_bs_bf, pl->d_bs_tw, st))
@@ -880,6 +933,9 @@ bool inverse_rows(qtam_plan_s* pl, int table, const void* y, int64_t segs, char*
       ok = launch_inv_rows_rowst<T>(ilog2(pl->r1), A, pack, pl->d_rows, pl->d_tab[table], hp.rows,
                                     segs * hp.rows, hp.sum_len, hp.n_out, pl->r2, pl->d_tw_r1, st);
     }
+  } else if (pl->bluestein && pl->bs_long) {
+    Timed tm(pl, K_INV_ROWS, st);
+    ok = chirp_rows_long<T>(pl, false, table, y, pack, segs, ws, lay, st);
   } else if (pl->bluestein) {
     Timed tm(pl, K_INV_ROWS, st);
     ok = launch_rows_bs<T>(false, ilog2(pl->bs_len), y, pack, pl->d_rows, pl->d_tab[table], hp.rows, segs * hp.rows,
@@ -934,9 +990,15 @@ bool synthesize(qtam_plan_s* pl, const void* pack, int64_t slen, const int* star
 }
 
 // Dense tiles of a chunk: the kept DFT_{N_out} slots of every row (scaled),
-// placed at their bins of an N-point row, then N-point inverse transforms:
-// placed in `dtmp` and transformed into `dense` (one pass), or placed in
-// `dense`, first pass into `dtmp`, second pass back into `dense`.
+// placed at their bins of an N-point row, then N-point inverse transforms.
+// N a power of two: placed in `dtmp` and transformed into `dense` (one pass),
+// or placed in `dense`, first pass into `dtmp`, second pass back into `dense`.
+// N = r * Md (r = 3, 5): the radix-r combination first (decimated rows
+// A_n1), then the Md-point transforms of the r rows, then the rows back to
+// the natural order:
+//   one pass:  place -> dtmp, radix -> dense, transform -> dtmp, permute -> dense;
+//   two passes: place -> dense, radix -> dtmp, pass 1 -> dense, pass 2 -> dtmp,
+//               permute -> dense.
 template <typename T>
 bool run_dense(qtam_plan_s* pl, const void* y, void* dense, int64_t segs, char* ws, const WsLayout& lay, void* dtmp,
                hipStream_t st) {
@@ -944,31 +1006,59 @@ bool run_dense(qtam_plan_s* pl, const void* y, void* dense, int64_t segs, char* 
   const HostPlan& hp = pl->hp;
   if (!inverse_rows<T>(pl, T_DENSE, y, segs, ws, lay, st)) return false;
   const int64_t count = segs * hp.rows;
+  const int r = pl->radix_r;
+  const int64_t md = pl->dense_md;
   {
     Timed tm(pl, K_DENSE_PLACE, st);
     hipLaunchKernelGGL((k_place<T>), dim3(unsigned((hp.n + 255) / 256), unsigned(count)), dim3(256), 0, st,
                        static_cast<const C*>(static_cast<void*>(ws + lay.pack)),
                        static_cast<C*>(pl->dense_four_step ? dense : dtmp), pl->d_rows, hp.rows, hp.n, hp.sum_len);
   }
+  // the buffer holding the placed rows, and the other one
+  void* a = pl->dense_four_step ? dense : dtmp;
+  void* b = pl->dense_four_step ? dtmp : dense;
+  if (r > 1) {
+    Timed tm(pl, K_DENSE_RADIX, st);
+    const dim3 grid(unsigned((md + 255) / 256), unsigned(count));
+    if (r == 3)
+      hipLaunchKernelGGL((k_radix<T, 3, +1, 1>), grid, dim3(256), 0, st, static_cast<const C*>(a),
+                         static_cast<C*>(b), md, tw2_of<T>(pl));
+    else if (r == 5)
+      hipLaunchKernelGGL((k_radix<T, 5, +1, 1>), grid, dim3(256), 0, st, static_cast<const C*>(a),
+                         static_cast<C*>(b), md, tw2_of<T>(pl));
+    else
+      return false;
+    std::swap(a, b);
+  }
+  // Md-point transforms of the rows in `a`, result in `b`
+  const int64_t rows = count * r;
+  bool ok;
   if (!pl->dense_four_step) {
     Timed tm(pl, K_DENSE_FFT, st);
-    return launch_fft_rows<T, +1>(ilog2(hp.n), dtmp, dense, count, hp.n, pl->d_tw_dense, st);
+    ok = launch_fft_rows<T, +1>(ilog2(md), a, b, rows, md, pl->d_tw_dense, st);
+  } else {
+    {
+      Timed tm(pl, K_DENSE_FFT1, st);
+      ok = launch_fft_cols<T, +1>(ilog2(pl->dn2), a, b, pl->dn1, rows, md, pl->d_tw_dn2, tw2_of<T>(pl), st, r);
+    }
+    if (ok) {
+      Timed tm(pl, K_DENSE_FFT2, st);
+      ok = launch_fft_rows_t<T, +1>(ilog2(pl->dn1), b, a, pl->dn2, rows, md, pl->d_tw_dn1, st);
+    }
+    std::swap(a, b);
   }
-  bool ok;
-  {
-    Timed tm(pl, K_DENSE_FFT1, st);
-    ok = launch_fft_cols<T, +1>(ilog2(pl->dn2), dense, dtmp, pl->dn1, count, hp.n, pl->d_tw_dn2, tw2_of<T>(pl), st, 1);
-  }
-  if (!ok) return false;
-  Timed tm(pl, K_DENSE_FFT2, st);
-  return launch_fft_rows_t<T, +1>(ilog2(pl->dn1), dtmp, dense, pl->dn2, count, hp.n, pl->d_tw_dn1, st);
+  if (!ok || r == 1) return ok;
+  Timed tm(pl, K_DENSE_PERM, st);
+  hipLaunchKernelGGL((k_permute<T, false>), dim3(unsigned((hp.n + 255) / 256), unsigned(count)), dim3(256), 0, st,
+                     static_cast<const C*>(b), static_cast<C*>(a), r, md);
+  return true;
 }
 
 // Segments per dense chunk: rows index grid.y, each chunk's tiles below 2 GiB.
 int64_t dense_chunk_cap(const qtam_plan_s* pl) {
   const HostPlan& hp = pl->hp;
   const size_t per = size_t(hp.rows) * size_t(hp.n) * (hp.precision == QTAM_FP64 ? 16 : 8);
-  int64_t cap = std::min<int64_t>(chunk_cap(pl), 65535 / hp.rows);
+  int64_t cap = std::min<int64_t>(chunk_cap(pl), 65535 / (int64_t(hp.rows) * pl->radix_r));
   cap = std::min<int64_t>(cap, per >= (size_t(1) << 31) ? 0 : int64_t(((size_t(1) << 31) - 1) / per));
   return cap;
 }
@@ -1047,13 +1137,23 @@ void choose_geometry(qtam_plan_s* pl) {
   const int max_single = f64 ? kMaxLog2Single64 : kMaxLog2Single32;
   pl->gpu_supported = false;
   pl->unsupported_reason = QTAM_ERR_UNSUPPORTED;
-  // N_out not a power of two: chirp-z rows of the next power of two >= 2 N_out - 1
+  // N_out not a power of two: chirp-z rows of the next power of two >= 2 N_out - 1,
+  // in one workgroup, or (longer) as r1 x r2 four-step transforms
   pl->bluestein = !is_pow2(hp.n_out);
+  pl->bs_long = false;
   if (pl->bluestein) {
     int64_t lb = 1;
     while (lb < 2 * int64_t(hp.n_out) - 1) lb *= 2;
     pl->bs_len = lb;
-    if (ilog2(lb) > max_single || ilog2(lb) < 2) return;
+    const int lg = ilog2(lb);
+    if (lg < 2) return;
+    if (lg > max_single) {
+      pl->bs_long = true;
+      const int l2 = lg / 2, l1 = lg - l2;   // bs_len = r1 * r2, r1 >= r2
+      pl->r1 = int64_t(1) << l1;
+      pl->r2 = int64_t(1) << l2;
+      if (l1 > (f64 ? kMaxLog2Col64 : kMaxLog2Col32) || l2 < 3 || hp.rows > 65535) return;
+    }
   }
   // N/2 = r * M2 with r in {1, 3, 5} and M2 a power of two
   pl->radix_r = 0;
@@ -1089,10 +1189,12 @@ void choose_geometry(qtam_plan_s* pl) {
   }
   pl->gpu_supported = true;
   pl->unsupported_reason = QTAM_OK;
-  // dense tiles: N-point transforms, one pass or N = dn1 * dn2
+  // dense tiles: N-point transforms, N = r * Md with the radix-r split of the
+  // spectrum (r = 1, 3, 5); the Md-point transforms in one pass or Md = dn1 * dn2
   pl->dense_ok = false;
-  if (is_pow2(hp.n)) {
-    const int lt = ilog2(hp.n);
+  pl->dense_md = hp.n / pl->radix_r;
+  {
+    const int lt = ilog2(pl->dense_md);
     if (lt <= max_single) {
       pl->dense_four_step = false;
       pl->dense_ok = true;

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void k_place(const typename Complex<T>::type* 
 }
 
 // Single-tile recovery: row `row` of each segment, its N_out-point forward
-// transform, every slot whose bin c = s + j lies in 0..N/2 times the tile
+// transform, every slot that holds a kept bin c (slot_entry) times the tile
 // table (sqrt(N/N_out) / W / N) into Sx[seg][c]. One segment per row group.
 template <typename T, int L>
 __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_tile_rows(
@@ -52,11 +52,10 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_tile_rows(
   C* dst = Sx + int64_t(seg) * (half + 1);
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) {
-    const int off = F::out_off(i);
-    const int c = rm.s + tl + (off < L / 2 ? off : off - L);
-    if (c >= rm.lo && c <= rm.hi) {
-      const T w = tab[rm.off + c - rm.lo];
-      dst[c] = C{v[i].x * w, v[i].y * w};
+    const int d = slot_entry<L>(tl + F::out_off(i), rm);
+    if (d <= rm.hi - rm.lo) {
+      const T w = tab[rm.off + d];
+      dst[rm.lo + d] = C{v[i].x * w, v[i].y * w};
     }
   }
 }
@@ -159,8 +158,9 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
   const int seg = ok ? gr / R : 0;
   const int row = ok ? gr - seg * R : 0;
   const RowMeta rm = rows[row];
+  const bool centred = row_centred(rm, L);
   C v[Geo::E];
-  if (kWaveRow && rm.lo > 0 && rm.hi < half) {
+  if (kWaveRow && rm.lo > 0 && rm.hi < half && centred) {
     const int len = rm.hi - rm.lo + 1;
     const rsrc_t rz = make_rsrc(spec + int64_t(seg) * half + rm.lo, ok ? static_cast<uint32_t>(len * sizeof(C)) : 0u);
     const rsrc_t rt = make_rsrc(tab + rm.off, ok ? static_cast<uint32_t>(len * sizeof(T)) : 0u);
@@ -184,14 +184,14 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
 
     const unsigned zb = static_cast<unsigned>(seg) * static_cast<unsigned>(half);
-    const int cb = rm.s + tl;
-    // X[c] of the slots in the kept support; other slots get an offset beyond
-    // the buffer and read 0 without touching memory
+    const int last = rm.hi - rm.lo;
+    // X[c] of the slots holding a kept bin c = lo + d; other slots get an
+    // offset beyond the buffer and read 0 without touching memory
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::in_off(i);
-      const int c = cb + (off < L / 2 ? off : off - L);   // slot tl + off holds offset j = slot or slot - L
-      const bool in = ok && c >= rm.lo && c <= rm.hi;
+      const int d = slot_entry<L>(tl + F::in_off(i), rm);
+      const int c = rm.lo + d;
+      const bool in = ok && d <= last;
       const unsigned vo = in ? (zb + static_cast<unsigned>(c == half ? 0 : c)) * static_cast<unsigned>(sizeof(C))
                              : 0xFFFFFFFFu;
       v[i] = bload<C>(rz, vo);
@@ -200,9 +200,9 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     if constexpr (ANALYTIC) sw = roww[row];   // (scale_k, 1/h_k)
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::in_off(i);
-      const int j = tl + (off < L / 2 ? off : off - L);
-      const int c = rm.s + j;
+      const int d = slot_entry<L>(tl + F::in_off(i), rm);
+      const int c = rm.lo + d;
+      const int j = c - rm.s;
       C val = v[i];
       if (c == 0) val.y = 0;               // slot 0 of the spectrum holds (X[0], X[N/2])
       if (c == half) val = C{val.y, 0};
@@ -212,13 +212,13 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
         const T b = (T(1) - x) * (T(1) + x);
         w = sw.x * b * b;
       } else {
-        const bool in = ok && c >= rm.lo && c <= rm.hi;
-        w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off - rm.lo + c : 0) * sizeof(T));
+        const bool in = ok && d <= last;
+        w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off + d : 0) * sizeof(T));
       }
       v[i] = C{val.x * w, val.y * w};
     }
   }
-  // Inputs outside the row's kept offsets [jlo, jhi] are zero; when every
+  // Inputs of a centred row outside its kept offsets [jlo, jhi] are zero; when every
   // lane of this wave has zeros in first-pass inputs 1..14 (or 2..13) the
   // first pass skips them (same results, fewer operations).
   int nz = 0;
@@ -227,7 +227,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const int t0 = __builtin_amdgcn_readfirstlane(tl) & ~63;
     constexpr int Q = L / 16;   // input i of lane tl sits at slot tl + i Q
     auto zero = [&](int a, int b) { return t0 + a * Q > jhi && t0 + 63 + b * Q < L + jlo; };
-    nz = zero(1, 14) ? 2 : (zero(2, 13) ? 4 : 0);
+    nz = !centred ? 0 : (zero(1, 14) ? 2 : (zero(2, 13) ? 4 : 0));
   }
   F::run(v, lds + g * fft_lds_elems<T, L>(), tl, F::twiddles(tw), nz);
   const int64_t r0 = int64_t(u) * Geo::G;
@@ -272,6 +272,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
     const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
     const rsrc_t rs = make_rsrc(Sbuf + int64_t(seg) * sum_len + rm.off, static_cast<uint32_t>(len * sizeof(C)));
     const rsrc_t rt = make_rsrc(tab + rm.off, static_cast<uint32_t>(len * sizeof(T)));
+    const bool centred = row_centred(rm, L);
     unsigned bs = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(C));
     unsigned bw = static_cast<unsigned>(db) * static_cast<unsigned>(sizeof(T));
     opaque(bs);
@@ -288,6 +289,17 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
       }
     }
     F::run(v, lds + g * fft_lds_elems<T, L>(), tl, F::twiddles(tw));
+    if (!centred) {
+      // a row of a regularised window: slot entries taken modulo L (the
+      // early weights above are not used)
+#pragma unroll
+      for (int i = 0; i < Geo::E; ++i) {
+        const unsigned d = static_cast<unsigned>(slot_entry<L>(tl + F::out_off(i), rm));
+        const T wi = bload<T>(rt, d * static_cast<unsigned>(sizeof(T)));
+        bstore<C, kSStore>(rs, C{v[i].x * wi, v[i].y * wi}, d * static_cast<unsigned>(sizeof(C)));
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
       const int off = F::out_off(i);
@@ -304,15 +316,13 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
     const int seg = gr / R;
     const RowMeta rm = rows[gr - seg * R];
     const int len = rm.hi - rm.lo + 1;
-    const int db = rm.s - rm.lo + tl;   // d = c - lo for the slot u = tl + off
     const rsrc_t rs = make_rsrc(Sbuf, static_cast<uint32_t>(int64_t(segs) * sum_len * sizeof(C)));
     const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
     const unsigned sb = static_cast<unsigned>(seg) * static_cast<unsigned>(sum_len) + static_cast<unsigned>(rm.off);
 #pragma unroll
     for (int i = 0; i < Geo::E; ++i) {
-      const int off = F::out_off(i);
-      const int d = db + (off < L / 2 ? off : off - L);
-      if (static_cast<unsigned>(d) < static_cast<unsigned>(len)) {
+      const int d = slot_entry<L>(tl + F::out_off(i), rm);
+      if (d < len) {
         const T w = bload<T>(rt, (rm.off + d) * sizeof(T));
         bstore<C, kSStore>(rs, C{v[i].x * w, v[i].y * w}, (sb + d) * sizeof(C));
       }
@@ -369,19 +379,22 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows_bs(
   const rsrc_t rz = make_rsrc(spec, static_cast<uint32_t>(spec_elems * sizeof(C)));
   const rsrc_t rt = make_rsrc(tab, static_cast<uint32_t>(sum_len * sizeof(T)));
   const unsigned zb = static_cast<unsigned>(seg) * static_cast<unsigned>(half);
+  // slot u holds the kept bin c = lo + d, d = (u + s - lo) mod M, if d <= hi - lo
+  int sh = (rm.s - rm.lo) % M;
+  if (sh < 0) sh += M;
   C v[Geo::E];
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) {
     const int u = tl + F::in_off(i);                 // Bluestein slot; < M holds data
-    const int j = u <= M / 2 ? u : u - M;            // offset from the centre bin
-    const int c = rm.s + j;
-    const bool in = ok && u < M && c >= rm.lo && c <= rm.hi;
+    const int d = u + sh < M ? u + sh : u + sh - M;
+    const int c = rm.lo + d;
+    const bool in = ok && u < M && d <= rm.hi - rm.lo;
     const unsigned vo = in ? (zb + static_cast<unsigned>(c == half ? 0 : c)) * static_cast<unsigned>(sizeof(C))
                            : 0xFFFFFFFFu;
     C x = bload<C>(rz, vo);
     if (c == 0) x.y = 0;
     if (c == half) x = C{x.y, 0};
-    const T w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off - rm.lo + c : 0) * sizeof(T));
+    const T w = bload<T>(rt, static_cast<uint32_t>(in ? rm.off + d : 0) * sizeof(T));
     const C a = chirp[u < M ? u : 0];   // x is 0 outside the support
     v[i] = c_mul(C{x.x * w, x.y * w}, a);
   }
@@ -426,17 +439,109 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows_bs(
   const int seg = gr / R;
   const RowMeta rm = rows[gr - seg * R];
   C* srow = Sbuf + int64_t(seg) * sum_len + rm.off;
+  int sh = (rm.s - rm.lo) % M;   // slot u holds kept entry d = (u + s - lo) mod M
+  if (sh < 0) sh += M;
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) {
     const int u = tl + Fi::out_off(i);
     if (u >= M) continue;
-    const int j = u <= M / 2 ? u : u - M;
-    const int c = rm.s + j;
-    if (c < rm.lo || c > rm.hi) continue;
+    const int d = u + sh < M ? u + sh : u + sh - M;
+    if (d > rm.hi - rm.lo) continue;
     const C z = c_mul(v[i], c_conj(chirp[u]));
-    const T w = tab[rm.off + c - rm.lo];
-    srow[c - rm.lo] = C{z.x * w, z.y * w};
+    const T w = tab[rm.off + d];
+    srow[d] = C{z.x * w, z.y * w};
   }
+}
+
+// Chirp-z rows whose convolution length L exceeds one workgroup's transform:
+// the products before and after the length-L cyclic convolution run as
+// element passes around four-step transforms through the workspace (rows of
+// L values, row gr = seg * R + k). Same identity and tables as above.
+// Forward, before: B[gr][u] = X[c] F_k[c] a[u] for the kept bin c of slot
+// u < M (slot_entry modulo M), 0 for the other u < L.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bs_fwd_prep(const typename Complex<T>::type* __restrict__ spec,
+                                                     typename Complex<T>::type* __restrict__ B,
+                                                     const RowMeta* __restrict__ rows, const T* __restrict__ tab,
+                                                     int R, int half, int M, int64_t L,
+                                                     const typename Complex<T>::type* __restrict__ chirp) {
+  using C = typename Complex<T>::type;
+  const int64_t u = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (u >= L) return;
+  const int64_t gr = blockIdx.y;
+  const int64_t seg = gr / R;
+  const RowMeta rm = rows[gr - seg * R];
+  C val{0, 0};
+  if (u < M) {
+    int sh = (rm.s - rm.lo) % M;
+    if (sh < 0) sh += M;
+    const int d = static_cast<int>(u) + sh < M ? static_cast<int>(u) + sh : static_cast<int>(u) + sh - M;
+    if (d <= rm.hi - rm.lo) {
+      const int c = rm.lo + d;
+      C x = spec[seg * half + (c == half ? 0 : c)];
+      if (c == 0) x.y = 0;                     // slot 0 of the spectrum holds (X[0], X[N/2])
+      if (c == half) x = C{x.y, 0};
+      const T w = tab[rm.off + d];
+      val = c_mul(C{x.x * w, x.y * w}, chirp[u]);
+    }
+  }
+  B[gr * L + u] = val;
+}
+
+// Inverse, before: B[gr][u] = Y[gr][u] conj(a[u]) for u < M, 0 for u < L.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bs_inv_prep(const typename Complex<T>::type* __restrict__ Y,
+                                                     typename Complex<T>::type* __restrict__ B, int M, int64_t L,
+                                                     const typename Complex<T>::type* __restrict__ chirp) {
+  using C = typename Complex<T>::type;
+  const int64_t u = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (u >= L) return;
+  const int64_t gr = blockIdx.y;
+  B[gr * L + u] = u < M ? c_mul(Y[gr * M + u], c_conj(chirp[u])) : C{0, 0};
+}
+
+// The spectrum of the convolution: B[gr][k] *= Bhat[k] (Bhat holds the 1/L).
+template <typename T>
+__global__ __launch_bounds__(256) void k_bs_mul(typename Complex<T>::type* __restrict__ B, int64_t L,
+                                                const typename Complex<T>::type* __restrict__ bhat) {
+  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (k >= L) return;
+  const int64_t i = int64_t(blockIdx.y) * L + k;
+  B[i] = c_mul(B[i], bhat[k]);
+}
+
+// Forward, after: Y[gr][m] = B[gr][m] a[m], m < M.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bs_fwd_post(const typename Complex<T>::type* __restrict__ B,
+                                                     typename Complex<T>::type* __restrict__ Y, int M, int64_t L,
+                                                     const typename Complex<T>::type* __restrict__ chirp) {
+  const int64_t m = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (m >= M) return;
+  const int64_t gr = blockIdx.y;
+  Y[gr * M + m] = c_mul(B[gr * L + m], chirp[m]);
+}
+
+// Inverse, after: the kept slots u < M times conj(a[u]) and the table into
+// the packed buffer Sbuf[seg * sum_len + off + d].
+template <typename T>
+__global__ __launch_bounds__(256) void k_bs_inv_post(const typename Complex<T>::type* __restrict__ B,
+                                                     typename Complex<T>::type* __restrict__ Sbuf,
+                                                     const RowMeta* __restrict__ rows, const T* __restrict__ tab,
+                                                     int R, int64_t sum_len, int M, int64_t L,
+                                                     const typename Complex<T>::type* __restrict__ chirp) {
+  using C = typename Complex<T>::type;
+  const int u = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  if (u >= M) return;
+  const int64_t gr = blockIdx.y;
+  const int64_t seg = gr / R;
+  const RowMeta rm = rows[gr - seg * R];
+  int sh = (rm.s - rm.lo) % M;
+  if (sh < 0) sh += M;
+  const int d = u + sh < M ? u + sh : u + sh - M;
+  if (d > rm.hi - rm.lo) return;
+  const C z = c_mul(B[gr * L + u], c_conj(chirp[u]));
+  const T w = tab[rm.off + d];
+  Sbuf[seg * sum_len + rm.off + d] = C{z.x * w, z.y * w};
 }
 
 // Rows longer than one workgroup's LDS transform (four-step over the
@@ -460,14 +565,13 @@ __global__ __launch_bounds__((ColGeom<T, L2>::NT)) void k_fwd_rows_cols(
   const int64_t seg = gr / R;
   const RowMeta rm = rows[int(gr - seg * R)];
   const C* Z = spec + seg * half;
-  const int64_t hn = n_out / 2;
   C v[Geo::E];
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) {
     const int64_t u = n1 + l1 * F::in_index(tl, i);
-    const int64_t c = rm.s + (u < hn ? u : u - n_out);
+    const int64_t c = rm.lo + ((u + rm.s - rm.lo) & (n_out - 1));   // kept bin of slot u, if <= hi
     C val{0, 0};
-    if (c >= rm.lo && c <= rm.hi) {
+    if (c <= rm.hi) {
       val = Z[c == half ? 0 : c];
       if (c == 0) val.y = 0;                  // slot 0 holds (X[0], X[N/2])
       if (c == half) val = C{val.y, 0};
@@ -516,12 +620,11 @@ __global__ __launch_bounds__((ColGeom<T, L1>::NT)) void k_inv_rows_rowst(
   const RowMeta rm = rows[int(gr - seg * R)];
   C* dst = Sbuf + seg * sum_len + rm.off - rm.lo;
   const T* tb = tab + rm.off - rm.lo;
-  const int64_t hn = n_out / 2;
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) {
     const int64_t m = k2_0 + cc + l2 * F::out_index(tl, i);
-    const int64_t c = rm.s + (m < hn ? m : m - n_out);
-    if (c >= rm.lo && c <= rm.hi) {
+    const int64_t c = rm.lo + ((m + rm.s - rm.lo) & (n_out - 1));   // kept bin of slot m, if <= hi
+    if (c <= rm.hi) {
       const T w = tb[c];
       dst[c] = C{v[i].x * w, v[i].y * w};
     }

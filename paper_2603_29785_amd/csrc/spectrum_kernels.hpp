@@ -195,7 +195,10 @@ __global__ __launch_bounds__(256) void k_twist(typename Complex<T>::type* __rest
 //   inverse:  A_n1[k2] = e^{+2 pi i n1 k2 / (N/2)} sum_k1 Z[k2 + M2 k1] e^{+2 pi i n1 k1 / r};
 //             z[n1 + r n2] = IDFT_M2(A_n1)[n2]
 // k_permute moves a segment between the natural order z[n] and the decimated
-// rows Zp[n1][n2] (TO_ROWS) or back; k_radix does the combination.
+// rows Zp[n1][n2] (TO_ROWS) or back; k_radix does the combination. The same
+// split serves full-length transforms of N = r * M points (the dense tiles):
+// then the twiddles are e^{-+2 pi i n1 k2 / N}, one step of the N-point table
+// per unit of n1 k2 (TSTEP = 1) instead of two.
 template <typename T, bool TO_ROWS>
 __global__ __launch_bounds__(256) void k_permute(const typename Complex<T>::type* __restrict__ in,
                                                  typename Complex<T>::type* __restrict__ out, int r, int64_t m2) {
@@ -223,7 +226,7 @@ __device__ __forceinline__ typename Complex<T>::type root_r(int k) {
   }
 }
 
-template <typename T, int R, int S>
+template <typename T, int R, int S, int TSTEP = 2>
 __global__ __launch_bounds__(256) void k_radix(const typename Complex<T>::type* __restrict__ in,
                                                typename Complex<T>::type* __restrict__ out, int64_t m2,
                                                Twiddle2<typename Complex<T>::type> tw2) {
@@ -237,7 +240,7 @@ __global__ __launch_bounds__(256) void k_radix(const typename Complex<T>::type* 
 #pragma unroll
     for (int n1 = 0; n1 < R; ++n1) {
       const C f = in[base + n1 * m2 + k2];
-      a[n1] = n1 == 0 ? f : c_mul(f, tw2(2 * n1 * k2));
+      a[n1] = n1 == 0 ? f : c_mul(f, tw2(TSTEP * n1 * k2));
     }
 #pragma unroll
     for (int k1 = 0; k1 < R; ++k1) {
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(256) void k_radix(const typename Complex<T>::type* 
       C acc = a[0];
 #pragma unroll
       for (int k1 = 1; k1 < R; ++k1) acc = c_add(acc, c_mul(a[k1], root_r<T, R>((n1 * k1) % R)));
-      b[n1] = n1 == 0 ? acc : c_mul(acc, c_conj(tw2(2 * n1 * k2)));
+      b[n1] = n1 == 0 ? acc : c_mul(acc, c_conj(tw2(TSTEP * n1 * k2)));
     }
 #pragma unroll
     for (int n1 = 0; n1 < R; ++n1) out[base + n1 * m2 + k2] = b[n1];

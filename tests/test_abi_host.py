@@ -170,18 +170,35 @@ def test_forward_sweep_validation_without_device():
     assert L.qtam_forward_sweep(None, 1, d, None, 1, d, ws, None) == binding.QTAM_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("fs,n,odd_n_out", [(4096.0, 2 * 7 * 1024, False), (16384.0, 1 << 20, True)])
-def test_unsupported_shapes_report_unsupported_not_invalid(fs, n, odd_n_out):
-    """N/2 with an odd factor other than 3 or 5, or a non-power-of-two N_out
-    (the longest window, the smallest valid one) whose chirp-z rows exceed
-    one workgroup: valid plans the GPU path does not run."""
-    kw = dict(sample_rate=fs, n_samples=n, q=8.0, f_min=20.0, f_max=min(4000.0, fs / 4), n_rows=62)
-    n_out = host_plan(**kw).info.max_len if odd_n_out else 0
-    assert not odd_n_out or n_out > 8192
-    gp = host_plan(n_out=n_out, **kw)
+def test_unsupported_shapes_report_unsupported_not_invalid():
+    """N/2 with an odd factor other than 3 or 5: a valid plan the GPU path
+    does not run."""
+    gp = host_plan(sample_rate=4096.0, n_samples=2 * 7 * 1024, q=8.0, f_min=20.0, f_max=1000.0, n_rows=62)
     dummy = ctypes.c_void_p(0x1000)
     st_ = binding.lib.qtam_forward(gp._h, dummy, dummy, 1, dummy, 1 << 30, None)
     assert st_ == binding.QTAM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("cap,n_out", [("cover", 0), ("paper", 13677)])
+def test_long_chirp_rows_are_supported(precision, cap, n_out):
+    """Odd N_out whose chirp-z convolution exceeds one workgroup (the long-
+    segment plan's smallest valid N_out, 27353, and the paper's minimal 13677
+    under the literal cap): supported, with two rows of the convolution
+    length per row and segment in the workspace."""
+    kw = dict(sample_rate=8192.0, n_samples=1 << 21, q=12.0, f_min=5.0, f_max=4096.0, n_rows=512,
+              cap_mode=cap, precision=precision)
+    if n_out == 0:
+        n_out = host_plan(**kw).info.max_len
+    assert n_out in (27353, 13677)
+    gp = host_plan(n_out=n_out, **kw)
+    L = 65536 if n_out == 27353 else 32768                 # next power of two >= 2 N_out - 1
+    cb = 16 if precision == "fp64" else 8
+    assert gp.info.workspace_bytes_per_segment >= 2 * 512 * L * cb
+    dummy = ctypes.c_void_p(0x1000)
+    # supported shape: a host-only plan fails on the missing device tables, not on the shape
+    st_ = binding.lib.qtam_forward(gp._h, dummy, dummy, 1, dummy, 1 << 34, None)
+    assert st_ == binding.QTAM_ERR_INVALID_ARG
 
 
 @pytest.mark.parametrize("n", [24576, 40960, 3 * 65536])

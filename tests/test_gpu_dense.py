@@ -35,6 +35,10 @@ CASES = [
     (1024.0, 4096, 8.0, 10.0, 400.0, 12, 3, 0),
     (4096.0, 32768, 16.0, 40.0, 500.0, 8, 2, 0),        # N beyond one workgroup: two passes
     (1024.0, 4096, 8.0, 10.0, 400.0, 12, 2, -1),        # odd N_out (chirp-z inverse rows)
+    # N = r * 2^k: radix-r combination around power-of-two transforms
+    (4096.0, 24576, 8.0, 20.0, 1000.0, 16, 2, 0),       # 6 s at 4096 Hz (the paper's segment), r = 3
+    (4096.0, 40960, 8.0, 100.0, 2048.0, 8, 1, 0),       # 10 s, r = 5, band to Nyquist
+    (4096.0, 196608, 32.0, 100.0, 200.0, 4, 1, 0),      # 48 s, r = 3 around two-pass 65536-point transforms
 ]
 
 
@@ -56,21 +60,21 @@ def test_dense_tiles_match_oracle(torch_dev, case, precision):
     D = gp.dense(gp.forward(xd)).cpu().numpy()
     assert D.shape == (B, R, n)
     T = np.stack([op.dense(xh[b]) for b in range(B)])
-    assert rel_rows(D, T).max() <= TOL[precision]
-    # from the oracle's envelopes
+    e1 = rel_rows(D, T).max()
+    # from the oracle's envelopes, cast to the device precision
     Yo = op.forward(xh)
     cdt = torch.complex128 if precision == "fp64" else torch.complex64
     D2 = gp.dense(torch.from_numpy(Yo).to(dtype=cdt, device="cuda")).cpu().numpy()
-    assert rel_rows(D2, T).max() <= TOL[precision]
+    e2 = rel_rows(D2, T).max()
+    print(f"  dense rel-L2: from the device forward {e1:.3e}, from the oracle's envelopes {e2:.3e}", flush=True)
+    assert e1 <= TOL[precision] and e2 <= TOL[precision]
 
 
-def test_dense_empty_and_unsupported(torch_dev):
+def test_dense_empty(torch_dev):
     torch = torch_dev
     import paper_2603_29785_amd as qt
     gp = qt.Plan(1024.0, 4096, 8.0, 10.0, 400.0, 12)
     y = torch.zeros((0, 12, gp.N_out), dtype=torch.complex64, device="cuda")
     assert gp.dense(y).shape == (0, 12, 4096)
-    bad = qt.Plan(4096.0, 24576, 8.0, 20.0, 1000.0, 16)          # N not a power of two
-    with pytest.raises(qt.QtamError) as e:
-        bad.dense(torch.zeros((1, 16, bad.N_out), dtype=torch.complex64, device="cuda"))
-    assert e.value.status == 2
+    g3 = qt.Plan(4096.0, 24576, 8.0, 20.0, 1000.0, 16)          # N = 3 * 8192
+    assert g3.dense(torch.zeros((0, 16, g3.N_out), dtype=torch.complex64, device="cuda")).shape == (0, 16, 24576)

@@ -36,16 +36,29 @@ def rel_rows(a, b):
     return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
 
 
+# (fs, N, N_out): N a power of two (N_out = N), the 6 s x 4096 Hz segment
+# (N/2 = 3 * 4096, N_out = 16384 < N) and N/2 = 5 * 512 (N_out = 4096 < N).
+# With N_out < N a row's band 0..N/2 reaches beyond N_out/2 on one side of
+# its centre for most rows, and only the wrap of slots (c - s) mod N_out
+# places those bins.
+SIZES = [(1024.0, 4096, 4096), (4096.0, 24576, 16384), (1024.0, 5120, 4096)]
+
+
+@pytest.mark.parametrize("fs,n,n_out", SIZES)
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_regularised_forward_inverse_and_single_tile(torch_dev, precision):
+def test_regularised_forward_inverse_and_single_tile(torch_dev, precision, fs, n, n_out):
     torch = torch_dev
     import paper_2603_29785_amd as qt
-    fs, n, q, fmin, fmax, R, B = 1024.0, 4096, 8.0, 10.0, 400.0, 16, 3
+    q, fmin, fmax, R, B = 8.0, 10.0, 400.0, 16, 3
     eps = EPS[precision]
     gp = qt.Plan(fs, n, q, fmin, fmax, R, precision=precision, window_eps=eps)
     op = o.OraclePlan(fs=fs, n=n, q=q, f_min=fmin, f_max=fmax, rows=R, eps=eps)
-    assert gp.N_out == op.N_out == n
-    print("regularised", precision, "eps", eps, flush=True)
+    assert gp.N_out == op.N_out == n_out
+    if n_out < n:
+        t = op.row_table()
+        off = (t["centre"] - t["lo"] > n_out // 2) | (t["hi"] - t["centre"] >= n_out // 2)
+        assert off.sum() >= R // 2
+    print("regularised", precision, "eps", eps, "N", n, "N_out", n_out, flush=True)
     x = np.stack([synthetic.injected_segment(n, fs, synthetic.rng_for(15, i))[0] for i in range(B)])
     dt = torch.float64 if precision == "fp64" else torch.float32
     cdt = torch.complex128 if precision == "fp64" else torch.complex64
@@ -58,6 +71,12 @@ def test_regularised_forward_inverse_and_single_tile(torch_dev, precision):
     Ych = Yc.cpu().numpy().astype(np.complex128)
     assert rel_rows(gp.inverse(Yc).cpu().numpy(), op.inverse(Ych)).max() <= TOL[precision]
     bar = 2000.0 * UNIT[precision] / eps
+    if precision == "fp64" and n_out > 8192:
+        # one-workgroup single-tile rows only (FP64: up to 8192 points)
+        with pytest.raises(qt.QtamError) as e:
+            gp.tile_inverse(Yc, 0)
+        assert e.value.status == 2
+        return
     for k in (0, R // 2, R - 1):
         xt = gp.tile_inverse(Yc, k).cpu().numpy()
         assert rel_rows(xt, op.tile_inverse(Ych, k)).max() <= bar, k

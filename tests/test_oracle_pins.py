@@ -503,11 +503,25 @@ def test_regularised_windows_and_single_tile_recovery():
         p0.tile_inverse(p0.forward(x), 2)
 
 
-def test_regularised_forward_matches_dense_definition():
+@pytest.mark.parametrize("n,f_min,f_max", [(256, 8.0, 50.0), (384, 5.0, 60.0), (640, 3.0, 62.0)])
+def test_regularised_forward_matches_dense_definition(n, f_min, f_max):
     """With eps the dense tile of the definition still equals the re-modulated
-    envelope (the full band is one kept support)."""
-    p = o.OraclePlan(fs=128.0, n=256, q=4.0, f_min=8.0, f_max=50.0, rows=5, eps=1e-3)
+    envelope (the full band is one kept support). N = 384 and 640 (N/2 = 3 and
+    5 times a power of two) give N_out = 256 and 512, shorter than N: a row's
+    band 0..N/2 then reaches further than N_out/2 on one side of its centre,
+    and the wrap of slots (c - s) mod N_out is what places it."""
+    p = o.OraclePlan(fs=128.0, n=n, q=4.0, f_min=f_min, f_max=f_max, rows=5, eps=1e-3)
+    assert p.N_out >= p.n // 2 + 1
+    t0 = p.row_table()
+    if n != 256:
+        assert p.N_out < p.n
+        off_centre = (t0["centre"] - t0["lo"] > p.N_out // 2) | (t0["hi"] - t0["centre"] >= p.N_out // 2)
+        assert off_centre.any()
     x = np.random.default_rng(42).standard_normal(p.n)
+    xs = np.stack([x, np.roll(x, 7)])
+    assert rel(p.inverse(p.forward(xs)), p.project(xs)) < 1e-12
+    for k in (0, p.R - 1):
+        assert rel(p.tile_inverse(p.forward(xs), k), xs) < 1e-9
     T = p.dense(x)
     Y = p.forward(x)
     t = p.row_table()
@@ -518,3 +532,15 @@ def test_regularised_forward_matches_dense_definition():
         for c in range(t["lo"][k], t["hi"][k] + 1):
             F[c] = Yt[(c - t["centre"][k]) % M]
         assert rel(np.fft.ifft(F), T[k]) < 1e-12
+
+
+def test_sampled_rows_are_the_full_forward_rows():
+    """forward_rows (the forward for chosen rows only, used where the oracle's
+    every-row transform is too slow) returns exactly those rows of forward."""
+    p = o.OraclePlan(fs=1024.0, n=4096, q=8.0, f_min=10.0, f_max=400.0, rows=16, n_out=201)
+    x = np.random.default_rng(43).standard_normal((2, p.n))
+    Y = p.forward(x)
+    assert np.array_equal(p.forward_rows(x, [3, 0, 15]), Y[:, [3, 0, 15]])
+    assert np.array_equal(p.forward_rows(x[1], [7]), Y[1, [7]])
+    with pytest.raises(IndexError):
+        p.forward_rows(x, [16])
