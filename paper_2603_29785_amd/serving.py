@@ -6,11 +6,19 @@ buffers on the device; a request waits in its bucket's queue and is launched,
 together with whatever else of that bucket is waiting, as soon as the bucket's
 slot buffers are free and a stream is free. Different buckets run on
 different streams at the same time, so requests that arrive while others are
-on the GPU are admitted as slots and memory free up. A bucket's batch runs as
-a replay of a captured graph (forward + inverse over the slot count rounded up
-to a power of two). Device memory is admitted by footprint: a bucket's
-resources are created only if they fit the budget, evicting idle buckets
-(least recently used) when needed.
+on the GPU are admitted as slots and memory free up. A bucket holds two slot
+sets (the executor's ``sets_per_bucket``), so arrivals to a bucket whose
+launch is in flight go out on the other set without waiting for it. A
+bucket's batch runs as a replay of a captured graph (forward + inverse over
+the slot count rounded up to a power of two). Device memory is admitted by
+footprint: a bucket's resources are created only if they fit the budget,
+evicting idle buckets (least recently used) when needed.
+
+Payloads: a request's samples may be a pinned host tensor (then the executor
+copies it to its slot with one asynchronous DMA, no host copy) or any array
+(staged through the bucket's pinned buffer). Results come back to the host
+by DMA into pinned memory; only requests with ``keep_result`` get a host
+copy of theirs.
 
 The scheduler (``Server``) is independent of the device: it drives an
 executor with ``footprint / prepare / release / launch / poll``. ``GpuExecutor``
@@ -52,6 +60,7 @@ class Request:
     finished: Optional[float] = None
     result: Any = None                 # reconstruction (host), set by the executor
     coeffs: Any = None                 # envelopes (host), if the executor keeps them
+    keep_result: bool = True           # False: latency only, no host copy of the result
 
     @property
     def latency(self) -> Optional[float]:
@@ -78,7 +87,8 @@ class Server:
         self.resources: Dict[BucketKey, Any] = {}      # prepared bucket -> executor handle
         self.footprints: Dict[BucketKey, int] = {}
         self.last_use: Dict[BucketKey, float] = {}
-        self.busy: Dict[BucketKey, Any] = {}           # bucket -> in-flight token
+        self.busy: Dict[BucketKey, List[Any]] = {}     # bucket -> its launches in flight
+        self.sets = max(1, int(getattr(executor, "sets_per_bucket", 1)))
         self.stream_busy = [None] * self.streams       # stream -> bucket in flight
         self.used = 0
         self.peak_used = 0
@@ -98,23 +108,26 @@ class Server:
         return req
 
     def pending(self) -> int:
-        return sum(len(q) for q in self.queues.values()) + len(self.busy)
+        return sum(len(q) for q in self.queues.values()) + sum(len(t) for t in self.busy.values())
 
     # -- one scheduling pass -----------------------------------------------
     def step(self) -> int:
         """Retire finished launches, drop expired requests, admit and launch.
         Returns the number of launches started."""
         now = self.clock()
-        for key, tok in list(self.busy.items()):
-            if self.ex.poll(tok):
-                t = self.clock()
-                for r in tok.requests:
-                    r.status = "done"
-                    r.finished = t
-                    self.done.append(r)
-                self.stream_busy[tok.stream] = None
+        for key, toks in list(self.busy.items()):
+            for tok in list(toks):
+                if self.ex.poll(tok):
+                    t = self.clock()
+                    for r in tok.requests:
+                        r.status = "done"
+                        r.finished = t
+                        self.done.append(r)
+                    self.stream_busy[tok.stream] = None
+                    toks.remove(tok)
+                    self.last_use[key] = t
+            if not toks:
                 del self.busy[key]
-                self.last_use[key] = t
         for key, q in self.queues.items():
             while q and q[0].deadline is not None and q[0].deadline < now:
                 r = q.popleft()
@@ -124,7 +137,7 @@ class Server:
         started = 0
         # oldest waiting request first
         order = sorted(((q[0].arrival, i, key) for i, (key, q) in enumerate(self.queues.items())
-                        if q and key not in self.busy), key=lambda e: (e[0], e[1]))
+                        if q and len(self.busy.get(key, ())) < self.sets), key=lambda e: (e[0], e[1]))
         for _, _, key in order:
             free = [i for i, b in enumerate(self.stream_busy) if b is None]
             if not free:
@@ -151,7 +164,7 @@ class Server:
             tok = self.ex.launch(self.resources[key], batch, free[0])
             tok.requests = batch
             tok.stream = free[0]
-            self.busy[key] = tok
+            self.busy.setdefault(key, []).append(tok)
             self.stream_busy[free[0]] = key
             self.last_use[key] = t
             self.launches += 1
@@ -204,8 +217,8 @@ class Server:
 
     def shutdown(self):
         for key in list(self.resources):
-            if key in self.busy:
-                while not self.ex.poll(self.busy[key]):
+            for tok in self.busy.pop(key, []):
+                while not self.ex.poll(tok):
                     self.ex.idle()
             self.ex.release(self.resources.pop(key))
         self.used = 0
@@ -236,11 +249,12 @@ class _Token:
 
 
 class GpuExecutor:
-    """MI355X executor: plans and slot buffers resident per bucket, one
-    captured graph of forward + inverse per (bucket, power-of-two slot count),
-    host staging in pinned memory, one HIP stream per server stream."""
+    """MI355X executor: plans resident per bucket and ``sets_per_bucket`` slot
+    sets (device buffers, workspace, pinned host staging) per bucket, one
+    captured graph of forward + inverse per (slot set, power-of-two slot
+    count), one HIP stream per server stream."""
 
-    def __init__(self, streams: int = 4, keep_coeffs: bool = False, device: str = "cuda"):
+    def __init__(self, streams: int = 4, keep_coeffs: bool = False, device: str = "cuda", sets_per_bucket: int = 2):
         import torch
         from .binding import Plan
         self.torch = torch
@@ -248,6 +262,7 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.keep_coeffs = keep_coeffs
+        self.sets_per_bucket = max(1, int(sets_per_bucket))
         self.plans: Dict[BucketKey, Any] = {}
 
     def _plan(self, key: BucketKey):
@@ -263,7 +278,7 @@ class GpuExecutor:
                                         precision=key.precision, host_only=True)
         b = 8 if key.precision == "fp64" else 4
         per = 2 * b * key.n + 2 * b * p.R * p.N_out
-        return slots * per + p.workspace_bytes(slots) + 32 * p.info.sum_len + 16 * p.info.n_bins
+        return self.sets_per_bucket * (slots * per + p.workspace_bytes(slots)) + 32 * p.info.sum_len + 16 * p.info.n_bins
 
     def prepare(self, key: BucketKey, slots: int):
         from .binding import QtamError, QTAM_ERR_UNSUPPORTED
@@ -276,24 +291,34 @@ class GpuExecutor:
             raise
         rdt = torch.float64 if p.fp64 else torch.float32
         cdt = torch.complex128 if p.fp64 else torch.complex64
-        res = dict(plan=p, slots=slots,
-                   x=torch.zeros(slots, key.n, dtype=rdt, device=self.device),
-                   y=torch.zeros(slots, p.R, p.N_out, dtype=cdt, device=self.device),
-                   xr=torch.zeros(slots, key.n, dtype=rdt, device=self.device),
-                   ws=torch.empty(p.workspace_bytes(slots), dtype=torch.uint8, device=self.device),
-                   hin=torch.zeros(slots, key.n, dtype=rdt).pin_memory(),
-                   hout=torch.zeros(slots, key.n, dtype=rdt).pin_memory(),
-                   graphs={})
-        return res
 
-    def _graph(self, res, count: int):
+        def slot_set():
+            return dict(x=torch.zeros(slots, key.n, dtype=rdt, device=self.device),
+                        y=torch.zeros(slots, p.R, p.N_out, dtype=cdt, device=self.device),
+                        xr=torch.zeros(slots, key.n, dtype=rdt, device=self.device),
+                        ws=torch.empty(p.workspace_bytes(slots), dtype=torch.uint8, device=self.device),
+                        hin=torch.zeros(slots, key.n, dtype=rdt, pin_memory=True),
+                        hout=torch.zeros(slots, key.n, dtype=rdt, pin_memory=True),
+                        graphs={}, in_use=False)
+
+        return dict(plan=p, slots=slots, dtype=rdt, sets=[slot_set() for _ in range(self.sets_per_bucket)])
+
+    def warm(self, res):
+        """Capture every graph of every slot set of a prepared bucket."""
+        for ss in res["sets"]:
+            n = 1
+            while n <= res["slots"]:
+                self._graph(res, ss, n)
+                n *= 2
+
+    def _graph(self, res, ss, count: int):
         torch = self.torch
         k = 1 << max(0, math.ceil(math.log2(max(count, 1))))
         k = min(k, res["slots"])
-        g = res["graphs"].get(k)
+        g = ss["graphs"].get(k)
         if g is None:
             p = res["plan"]
-            x, y, xr, ws = res["x"][:k], res["y"][:k], res["xr"][:k], res["ws"]
+            x, y, xr, ws = ss["x"][:k], ss["y"][:k], ss["xr"][:k], ss["ws"]
             s = torch.cuda.Stream(device=self.device)
             s.wait_stream(torch.cuda.current_stream(self.device))
             with torch.cuda.stream(s):      # warm-up outside capture
@@ -306,7 +331,7 @@ class GpuExecutor:
                 p.forward(x, out=y, ws=ws, stream=cs)
                 p.inverse(y, out=xr, ws=ws, stream=cs)
             torch.cuda.synchronize(self.device)
-            res["graphs"][k] = g
+            ss["graphs"][k] = g
         return g, k
 
     def release(self, res):
@@ -316,32 +341,39 @@ class GpuExecutor:
         torch = self.torch
         s = self.streams[stream_idx]
         n = len(batch)
-        g, k = self._graph(res, n)
-        for i, r in enumerate(batch):
-            res["hin"][i].copy_(torch.as_tensor(r.data, dtype=res["hin"].dtype))
+        ss = next(x for x in res["sets"] if not x["in_use"])
+        g, k = self._graph(res, ss, n)
         tok = _Token()
         with torch.cuda.stream(s):
-            res["x"][:n].copy_(res["hin"][:n], non_blocking=True)
+            for i, r in enumerate(batch):
+                d = r.data
+                if isinstance(d, torch.Tensor) and d.is_pinned() and d.dtype == res["dtype"]:
+                    ss["x"][i].copy_(d, non_blocking=True)           # DMA from the request's pinned payload
+                else:
+                    ss["hin"][i].copy_(torch.as_tensor(d, dtype=res["dtype"]))
+                    ss["x"][i].copy_(ss["hin"][i], non_blocking=True)
             g.replay()
             tok.event = torch.cuda.Event()
             tok.event.record(s)
-            res["hout"][:n].copy_(res["xr"][:n], non_blocking=True)
+            ss["hout"][:n].copy_(ss["xr"][:n], non_blocking=True)
             if self.keep_coeffs:
-                tok.coeffs = res["y"][:n].clone()
+                tok.coeffs = ss["y"][:n].clone()
             tok.copied = torch.cuda.Event()
             tok.copied.record(s)
-        tok.res = res
+        ss["in_use"] = True
+        tok.set = ss
         tok.count = n
         return tok
 
     def poll(self, tok) -> bool:
-        if not tok.event.query():
+        if not tok.copied.query():
             return False
-        tok.copied.synchronize()
         for i, r in enumerate(tok.requests):
-            r.result = tok.res["hout"][i].numpy().copy()
+            if r.keep_result:
+                r.result = tok.set["hout"][i].numpy().copy()
             if self.keep_coeffs:
                 r.coeffs = tok.coeffs[i].cpu().numpy()
+        tok.set["in_use"] = False
         return True
 
     def idle(self):

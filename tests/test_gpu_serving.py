@@ -27,17 +27,19 @@ def test_graph_replays_match_eager(torch_dev):
     x = torch.from_numpy(synthetic.batched_segments(4, 16384, 4096.0, workload=7)).cuda()
     p = res["plan"]
     eager = p.inverse(p.forward(x)).clone()
-    res["x"].copy_(x)
-    g, k = ex._graph(res, 4)
-    assert k == 4
-    for rep in range(3):
-        res["xr"].zero_()
-        g.replay()
-        torch.cuda.synchronize()
-        assert torch.equal(res["xr"], eager), rep
-        # eager work between replays on the same buffers
-        p.forward(x[:2].contiguous())
-        torch.cuda.synchronize()
+    assert len(res["sets"]) == 2
+    for ss in res["sets"]:
+        ss["x"].copy_(x)
+        g, k = ex._graph(res, ss, 4)
+        assert k == 4
+        for rep in range(3):
+            ss["xr"].zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(ss["xr"], eager), rep
+            # eager work between replays on the same buffers
+            p.forward(x[:2].contiguous())
+            torch.cuda.synchronize()
 
 
 def test_alone_equals_mix(torch_dev):
@@ -52,6 +54,8 @@ def test_alone_equals_mix(torch_dev):
         rows = int(rng.choice([64, 128]))
         key = BucketKey(fs, n, q, rows, 10.0, 2048.0)
         data = synthetic.injected_segment(n, fs, synthetic.rng_for(8, i))[0].astype(np.float32)
+        if i % 2:       # half the payloads in pinned host memory (copied by DMA), half staged
+            data = torch.from_numpy(data).pin_memory()
         reqs.append(Request(i, key, data))
     srv = Server(GpuExecutor(streams=4), hbm_budget=8 << 30, streams=4)
     for r in reqs:
@@ -60,7 +64,7 @@ def test_alone_equals_mix(torch_dev):
     srv.shutdown()
     assert all(r.status == "done" for r in reqs), [r.status for r in reqs]
     assert srv.launches < len(reqs)           # batched
-    alone = [Request(r.rid, r.key, r.data) for r in reqs]
+    alone = [Request(r.rid, r.key, np.asarray(r.data)) for r in reqs]
     plain_run(alone)
     for r, a in zip(reqs, alone):
         assert np.array_equal(r.result, a.result), r.rid
@@ -68,5 +72,5 @@ def test_alone_equals_mix(torch_dev):
     for r in reqs[:4]:
         k = r.key
         op = o.OraclePlan(fs=k.fs, n=k.n, q=k.q, f_min=k.f_min, f_max=k.f_max, rows=k.rows)
-        xm = op.project(r.data.astype(np.float64))
+        xm = op.project(np.asarray(r.data, dtype=np.float64))
         assert np.linalg.norm(r.result - xm) <= 1e-5 * np.linalg.norm(xm)

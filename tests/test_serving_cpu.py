@@ -164,3 +164,36 @@ def test_continuous_arrivals_and_stats():
     # requests that arrived while others ran were batched into later launches
     assert srv.launches < 60
     assert math.isfinite(s["samples_per_s"])
+
+
+def test_two_slot_sets_let_a_busy_bucket_launch_again():
+    """With two slot sets per bucket, requests arriving while the bucket's
+    first launch runs go out at once on the second set (and overlap it on
+    another stream); a third launch waits until one of them retires."""
+    c = Clock()
+    ex = FakeExecutor(c)
+    ex.sets_per_bucket = 2
+    srv = Server(ex, hbm_budget=1 << 40, streams=4, max_slots=2, clock=c)
+    k = key(1 << 20)
+    srv.submit(make(0, k))
+    srv.step()
+    srv.submit(make(1, k))
+    srv.submit(make(2, k))
+    srv.step()
+    assert len(ex.launch_log) == 2 and ex.in_flight == 2            # second set in flight beside the first
+    assert {s for (_, _, s, _) in ex.launch_log} == {0, 1}
+    srv.submit(make(3, k))
+    srv.step()
+    assert len(ex.launch_log) == 2                                  # both sets busy: request 3 waits
+    srv.drain()
+    assert [b for (_, b, _, _) in ex.launch_log] == [1, 2, 1]
+    assert sorted(r.rid for r in srv.done) == [0, 1, 2, 3] and all(r.status == "done" for r in srv.done)
+    # one set: the second launch waits for the first
+    c2 = Clock()
+    ex1 = FakeExecutor(c2)
+    srv1 = Server(ex1, hbm_budget=1 << 40, streams=4, max_slots=2, clock=c2)
+    srv1.submit(make(0, k))
+    srv1.step()
+    srv1.submit(make(1, k))
+    srv1.step()
+    assert len(ex1.launch_log) == 1
