@@ -162,6 +162,23 @@ size_t qtam_workspace_size(qtam_plan_t plan, int64_t batch);
 qtam_status qtam_forward(qtam_plan_t plan, const void* x, void* y, int64_t batch,
                          void* ws, size_t ws_bytes, qtam_stream_t stream);
 
+/* Forward transform that allocates nothing, for callers that cannot call
+ * hipMalloc: code under stream capture, tight serving loops, harnesses that
+ * forbid allocation. Same arguments and results as qtam_forward without a
+ * workspace: the library uses a static device array of
+ * QTAM_NOALLOC_WORKSPACE_BYTES that every device it runs on holds until the
+ * process ends (its address is looked up once per device at plan creation).
+ * The batch is processed in chunks that fit that array; a plan one segment
+ * of which needs more (qtam_workspace_size(plan, 1) above the size) returns
+ * QTAM_ERR_WORKSPACE, with the sizes in qtam_last_error. Every call on one
+ * device shares the array and every region of it is written before it is
+ * read (nothing is cleared): calls that overlap on one device (different
+ * streams, or several host threads) race; serialize them, for example on one
+ * stream. Launches of this call are not timed by qtam_timing_enable.        */
+#define QTAM_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+qtam_status qtam_forward_noalloc(qtam_plan_t plan, const void* x, void* y, int64_t batch,
+                                 qtam_stream_t stream);
+
 /* Inverse transform by the canonical dual frame (Sec. III; App. C):
  * y [batch, R, N_out] complex -> x [batch, N] real. Any y is accepted; the
  * result is the minimum-norm (canonical dual) synthesis restricted to M.    */

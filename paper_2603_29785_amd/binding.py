@@ -89,12 +89,15 @@ class c_info(ctypes.Structure):
     ]
 
 
+# Size of the static device workspace of qtam_forward_noalloc (QTAM_NOALLOC_WORKSPACE_BYTES).
+NOALLOC_WORKSPACE_BYTES = 64 << 20
+
 EXPORTED = [
     "qtam_plan_create", "qtam_plan_info", "qtam_plan_destroy", "qtam_workspace_size",
     "qtam_forward", "qtam_inverse", "qtam_forward_adjoint", "qtam_inverse_adjoint",
     "qtam_forward_metric", "qtam_select_planes", "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string",
     "qtam_dense", "qtam_dense_workspace_size", "qtam_tile_inverse", "qtam_last_error", "qtam_version",
-    "qtam_forward_sweep",
+    "qtam_forward_sweep", "qtam_forward_noalloc",
 ]
 
 
@@ -119,6 +122,8 @@ def _load():
         f = getattr(L, name)
         f.argtypes = [vp, vp, vp, i64, vp, sz, vp]
         f.restype = ctypes.c_int
+    L.qtam_forward_noalloc.argtypes = [vp, vp, vp, i64, vp]
+    L.qtam_forward_noalloc.restype = ctypes.c_int
     L.qtam_tile_inverse.argtypes = [vp, vp, ctypes.c_int32, vp, i64, vp, sz, vp]
     L.qtam_tile_inverse.restype = ctypes.c_int
     L.qtam_dense.argtypes = [vp, vp, vp, i64, vp, sz, vp]
@@ -393,6 +398,21 @@ class Plan:
         batch = int(np.prod(lead)) if len(lead) else 1
         y = self._out(out, tuple(lead) + (self.R, self.N_out), self._complex_dtype(), x.device)
         self._call(lib.qtam_forward, "qtam_forward", x, y, batch, ws, stream)
+        return y
+
+    def forward_noalloc(self, x, out=None, stream=None):
+        """forward() through qtam_forward_noalloc: the library's static device
+        workspace instead of a caller workspace (the call itself allocates
+        nothing; pass `out` to allocate nothing here either)."""
+        torch = self._torch()
+        x = self._check_signal(x)
+        lead = x.shape[:-1]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        y = self._out(out, tuple(lead) + (self.R, self.N_out), self._complex_dtype(), x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        _check(lib.qtam_forward_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                        int(batch), ctypes.c_void_p(stream.cuda_stream)), "qtam_forward_noalloc")
         return y
 
     def forward_metric(self, x, out=None, metric=None, ws=None, stream=None):

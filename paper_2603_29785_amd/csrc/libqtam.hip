@@ -83,6 +83,10 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // Text of the last HIP failure seen on this thread (qtam_last_error).
 thread_local std::string g_last_error;
 
+// Set while qtam_forward_noalloc runs on this thread: its launches are not
+// timed (timing may create events).
+thread_local bool g_untimed = false;
+
 qtam_status hip_failed(hipError_t e, const char* what, qtam_status st = QTAM_ERR_DEVICE) {
   g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
   (void)hipGetLastError();
@@ -428,7 +432,7 @@ struct Timed {
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
   Timed(qtam_plan_s* p, int k, hipStream_t st) : pl(p), kind(k), s(st) {
-    if (!pl->timing) return;
+    if (!pl->timing || g_untimed) return;
     std::lock_guard<std::mutex> g(pl->mu);
     for (hipEvent_t* e : {&a, &b}) {
       if (!pl->pool.empty()) {
@@ -1213,6 +1217,43 @@ void choose_geometry(qtam_plan_s* pl) {
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// Static workspace of qtam_forward_noalloc: a device array of fixed size that
+// every device the library runs on holds until the process ends. Host code
+// never passes `scratch` itself to a kernel (in host code the name is a
+// host-side stand-in): its device address, per device, comes from
+// hipGetSymbolAddress once at plan creation with that device current.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = QTAM_NOALLOC_WORKSPACE_BYTES;
+static_assert(kScratchBytes % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Looks up this device's scratch address once (the device is current).
+qtam_status scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return QTAM_OK;   // no static workspace on such devices
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return QTAM_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_failed(e, "hipGetSymbolAddress of the static workspace");
+  g_scratch_ptr[device] = ptr;
+  return QTAM_OK;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* qtam_last_error(void) { return g_last_error.c_str(); }
@@ -1256,6 +1297,11 @@ qtam_status qtam_plan_create(const qtam_params* params, qtam_plan_t* out) {
       pl->num_cus = 1;
     }
     pl->analytic_fwd = pl->hp.all_bisquare && pl->hp.eps == 0.0;
+    st = scratch_setup(pl->device_id);
+    if (st != QTAM_OK) {
+      delete pl;
+      return st;
+    }
     st = pl->hp.precision == QTAM_FP64 ? upload<double>(pl) : upload<float>(pl);
     if (st != QTAM_OK) {
       if (pl->dmem) (void)hipFree(pl->dmem);
@@ -1317,6 +1363,25 @@ size_t qtam_workspace_size(qtam_plan_t pl, int64_t batch) {
 qtam_status qtam_forward(qtam_plan_t pl, const void* x, void* y, int64_t batch, void* ws, size_t ws_bytes,
                          qtam_stream_t stream) {
   return run_op(pl, OP_FORWARD, x, y, batch, ws, ws_bytes, stream);
+}
+
+qtam_status qtam_forward_noalloc(qtam_plan_t pl, const void* x, void* y, int64_t batch, qtam_stream_t stream) {
+  if (!pl || batch < 0) return QTAM_ERR_INVALID_ARG;
+  if (!pl->gpu_supported) return pl->unsupported_reason;
+  if (pl->seg_bytes > kScratchBytes) {
+    g_last_error = "qtam_forward_noalloc: one segment of this plan needs " + std::to_string(pl->seg_bytes) +
+                   " workspace bytes, above the static workspace of " + std::to_string(kScratchBytes);
+    return QTAM_ERR_WORKSPACE;
+  }
+  if (batch == 0) return QTAM_OK;
+  if (!pl->device) return QTAM_ERR_INVALID_ARG;
+  void* ws = scratch_of(pl->device_id);
+  if (!ws) return QTAM_ERR_INVALID_ARG;
+  // every region of the workspace is written before it is read: nothing to clear
+  g_untimed = true;
+  const qtam_status st = run_op(pl, OP_FORWARD, x, y, batch, ws, kScratchBytes, stream);
+  g_untimed = false;
+  return st;
 }
 
 qtam_status qtam_forward_metric(qtam_plan_t pl, const void* x, void* y, void* metric, int64_t batch, void* ws,

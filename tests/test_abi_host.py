@@ -299,3 +299,25 @@ def test_output_and_workspace_checks():
         binding.expect_workspace(torch.empty(2048, dtype=torch.uint8)[::2], dev)
     with pytest.raises(ValueError):
         binding.expect_workspace(bytearray(16), dev)
+
+
+def test_noalloc_forward_rejects_plans_beyond_its_workspace():
+    """qtam_forward_noalloc checks the plan against its static workspace before
+    touching the device: a plan one segment of which needs more (the
+    long-segment plan in FP64: two-pass rows) gets QTAM_ERR_WORKSPACE with the
+    sizes in qtam_last_error; a plan that fits but has no device tables gets
+    QTAM_ERR_INVALID_ARG."""
+    big = host_plan(sample_rate=8192.0, n_samples=1 << 21, q=12.0, f_min=5.0, f_max=4096.0, n_rows=512,
+                    precision="fp64")
+    hdr = open(os.path.join(ROOT, "include", "qtam.h")).read()
+    m = re.search(r"#define QTAM_NOALLOC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == binding.NOALLOC_WORKSPACE_BYTES
+    assert big.workspace_bytes(1) > binding.NOALLOC_WORKSPACE_BYTES
+    dummy = ctypes.c_void_p(0x1000)
+    assert binding.lib.qtam_forward_noalloc(big._h, dummy, dummy, 1, None) == binding.QTAM_ERR_WORKSPACE
+    msg = binding.lib.qtam_last_error().decode()
+    assert "qtam_forward_noalloc" in msg and str(binding.NOALLOC_WORKSPACE_BYTES) in msg
+    small = host_plan(sample_rate=4096.0, n_samples=16384, q=8.0, f_min=20.0, f_max=1000.0, n_rows=64)
+    assert small.workspace_bytes(1) <= binding.NOALLOC_WORKSPACE_BYTES
+    assert binding.lib.qtam_forward_noalloc(small._h, dummy, dummy, 1, None) == binding.QTAM_ERR_INVALID_ARG
+    assert binding.lib.qtam_forward_noalloc(None, dummy, dummy, 1, None) == binding.QTAM_ERR_INVALID_ARG
