@@ -54,7 +54,7 @@ typedef enum {
   QTAM_ERR_INVALID_ARG = 1,   /* bad parameter, NULL pointer, or n_out < max L_k */
   QTAM_ERR_UNSUPPORTED = 2,   /* valid but not implemented on the GPU (e.g. size) */
   QTAM_ERR_WORKSPACE = 3,     /* workspace smaller than one segment needs */
-  QTAM_ERR_OOM = 4,           /* device allocation of plan tables failed */
+  QTAM_ERR_OOM = 4,           /* plan tables: device or host allocation failed */
   QTAM_ERR_DEVICE = 5         /* HIP runtime / launch error, or no device */
 } qtam_status;
 
@@ -271,9 +271,11 @@ qtam_status qtam_timing_collect(qtam_plan_t plan, const char** names, double* to
 
 const char* qtam_status_string(qtam_status status);
 
-/* Text of the last HIP runtime failure behind a QTAM_ERR_DEVICE or QTAM_ERR_OOM
- * returned on the calling thread (call name, HIP error name and message);
- * empty if none. Valid until the next call on this thread.                */
+/* Text of the last failure behind a QTAM_ERR_DEVICE or QTAM_ERR_OOM (and the
+ * sizes behind qtam_forward_noalloc's QTAM_ERR_WORKSPACE) returned on the
+ * calling thread: call name, HIP error name and message, or the host
+ * allocation that failed; empty if none. Valid until the next call on this
+ * thread.                                                                   */
 const char* qtam_last_error(void);
 
 /* Library version string, e.g. "qtam-gfx950 1.0".                           */

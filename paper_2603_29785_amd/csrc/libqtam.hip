@@ -448,7 +448,12 @@ struct Timed {
     if (!a || !b) return;
     (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> g(pl->mu);
-    pl->pending.push_back({kind, a, b});
+    try {
+      pl->pending.push_back({kind, a, b});
+    } catch (const std::bad_alloc&) {   // no room to keep the record: the launch goes untimed
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
   }
 };
 
@@ -1254,6 +1259,55 @@ void* scratch_of(int device) {
 
 }  // namespace
 
+namespace {
+
+// Plan creation proper; host allocations may throw std::bad_alloc, which
+// qtam_plan_create turns into QTAM_ERR_OOM (*made holds the plan to free).
+qtam_status create_plan(const qtam_params* params, qtam_plan_t* out, qtam_plan_s** made) {
+  qtam_plan_s* pl = new qtam_plan_s();
+  *made = pl;
+  qtam_status st = build_host_plan(*params, pl->hp);
+  if (st != QTAM_OK) {
+    delete pl;
+    *made = nullptr;
+    return st;
+  }
+  choose_geometry(pl);
+  pl->seg_bytes = layout_for(pl, 1).total;
+  if (!(params->flags & QTAM_PLAN_HOST_ONLY) && pl->gpu_supported) {
+    const hipError_t e = hipGetDevice(&pl->device_id);
+    if (e != hipSuccess) {
+      delete pl;
+      *made = nullptr;
+      return hip_failed(e, "hipGetDevice");
+    }
+    if (hipDeviceGetAttribute(&pl->num_cus, hipDeviceAttributeMultiprocessorCount, pl->device_id) != hipSuccess ||
+        pl->num_cus < 1) {
+      (void)hipGetLastError();
+      pl->num_cus = 1;
+    }
+    pl->analytic_fwd = pl->hp.all_bisquare && pl->hp.eps == 0.0;
+    st = scratch_setup(pl->device_id);
+    if (st != QTAM_OK) {
+      delete pl;
+      *made = nullptr;
+      return st;
+    }
+    st = pl->hp.precision == QTAM_FP64 ? upload<double>(pl) : upload<float>(pl);
+    if (st != QTAM_OK) {
+      if (pl->dmem) (void)hipFree(pl->dmem);
+      delete pl;
+      *made = nullptr;
+      return st;
+    }
+    pl->device = true;
+  }
+  *out = pl;
+  return QTAM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* qtam_last_error(void) { return g_last_error.c_str(); }
@@ -1266,7 +1320,7 @@ const char* qtam_status_string(qtam_status s) {
     case QTAM_ERR_INVALID_ARG: return "invalid argument";
     case QTAM_ERR_UNSUPPORTED: return "unsupported on this device path";
     case QTAM_ERR_WORKSPACE: return "workspace too small";
-    case QTAM_ERR_OOM: return "device out of memory";
+    case QTAM_ERR_OOM: return "out of memory (device, or host tables)";
     case QTAM_ERR_DEVICE: return "HIP device error";
   }
   return "unknown status";
@@ -1276,42 +1330,19 @@ qtam_status qtam_plan_create(const qtam_params* params, qtam_plan_t* out) {
   if (!out) return QTAM_ERR_INVALID_ARG;
   *out = nullptr;
   if (!params) return QTAM_ERR_INVALID_ARG;
-  qtam_plan_s* pl = new (std::nothrow) qtam_plan_s();
-  if (!pl) return QTAM_ERR_OOM;
-  qtam_status st = build_host_plan(*params, pl->hp);
-  if (st != QTAM_OK) {
-    delete pl;
-    return st;
+  qtam_plan_s* made = nullptr;
+  try {
+    return create_plan(params, out, &made);
+  } catch (const std::bad_alloc&) {
+    // host tables too large: nothing leaks, nothing crosses the C boundary
+    if (made) {
+      if (made->dmem) (void)hipFree(made->dmem);
+      delete made;
+    }
+    *out = nullptr;
+    g_last_error = "qtam_plan_create: host memory exhausted building the plan tables";
+    return QTAM_ERR_OOM;
   }
-  choose_geometry(pl);
-  pl->seg_bytes = layout_for(pl, 1).total;
-  if (!(params->flags & QTAM_PLAN_HOST_ONLY) && pl->gpu_supported) {
-    const hipError_t e = hipGetDevice(&pl->device_id);
-    if (e != hipSuccess) {
-      delete pl;
-      return hip_failed(e, "hipGetDevice");
-    }
-    if (hipDeviceGetAttribute(&pl->num_cus, hipDeviceAttributeMultiprocessorCount, pl->device_id) != hipSuccess ||
-        pl->num_cus < 1) {
-      (void)hipGetLastError();
-      pl->num_cus = 1;
-    }
-    pl->analytic_fwd = pl->hp.all_bisquare && pl->hp.eps == 0.0;
-    st = scratch_setup(pl->device_id);
-    if (st != QTAM_OK) {
-      delete pl;
-      return st;
-    }
-    st = pl->hp.precision == QTAM_FP64 ? upload<double>(pl) : upload<float>(pl);
-    if (st != QTAM_OK) {
-      if (pl->dmem) (void)hipFree(pl->dmem);
-      delete pl;
-      return st;
-    }
-    pl->device = true;
-  }
-  *out = pl;
-  return QTAM_OK;
 }
 
 qtam_status qtam_plan_info(qtam_plan_t pl, qtam_plan_info_t* info) {

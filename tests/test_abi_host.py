@@ -321,3 +321,24 @@ def test_noalloc_forward_rejects_plans_beyond_its_workspace():
     assert small.workspace_bytes(1) <= binding.NOALLOC_WORKSPACE_BYTES
     assert binding.lib.qtam_forward_noalloc(small._h, dummy, dummy, 1, None) == binding.QTAM_ERR_INVALID_ARG
     assert binding.lib.qtam_forward_noalloc(None, dummy, dummy, 1, None) == binding.QTAM_ERR_INVALID_ARG
+
+
+def test_plan_host_allocation_failure_is_oom():
+    """A plan whose host tables cannot be allocated (2^44 samples: the frame
+    operator alone would take 64 TiB) returns QTAM_ERR_OOM instead of letting
+    the allocation failure cross the C boundary; the host then stays usable.
+    Skipped where such an allocation would succeed untouched (a permissive
+    overcommit policy), so the test never commits that memory."""
+    libc = ctypes.CDLL("libc.so.6")
+    libc.malloc.restype = ctypes.c_void_p
+    libc.malloc.argtypes = [ctypes.c_size_t]
+    libc.free.argtypes = [ctypes.c_void_p]
+    probe = libc.malloc(1 << 46)
+    if probe:
+        libc.free(probe)
+        pytest.skip("64 TiB malloc succeeds here (overcommit): not forcing the failure")
+    with pytest.raises(qt.QtamError) as e:
+        host_plan(sample_rate=float(1 << 40), n_samples=1 << 44, q=8.0, f_min=100.0, f_max=200.0, n_rows=1)
+    assert e.value.status == binding.QTAM_ERR_OOM
+    assert "host memory" in binding.lib.qtam_last_error().decode()
+    assert host_plan(sample_rate=4096.0, n_samples=16384, q=8.0, f_min=20.0, f_max=1000.0, n_rows=64).R == 64
