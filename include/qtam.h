@@ -200,9 +200,8 @@ qtam_status qtam_inverse_adjoint(qtam_plan_t plan, const void* gx, void* gy, int
  * (Sec. III, regularised windows): X[c] = sqrt(N/N_out) DFT_{N_out}(Y_row)
  * [(c - s_row) mod N_out] / W_row[c] on every bin, then the inverse real FFT.
  * y [batch, R, N_out] -> x [batch, N]. Needs window_eps > 0
- * (QTAM_ERR_INVALID_ARG otherwise) and a power-of-two N_out of at most
- * 16384 (FP32) or 8192 (FP64) points (QTAM_ERR_UNSUPPORTED otherwise);
- * workspace as qtam_inverse.                                                */
+ * (QTAM_ERR_INVALID_ARG otherwise) and a power-of-two N_out (chirp-z
+ * lengths: QTAM_ERR_UNSUPPORTED); workspace as qtam_inverse.               */
 qtam_status qtam_tile_inverse(qtam_plan_t plan, const void* y, int32_t row, void* x, int64_t batch,
                               void* ws, size_t ws_bytes, qtam_stream_t stream);
 

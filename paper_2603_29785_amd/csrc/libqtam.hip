@@ -1077,15 +1077,44 @@ size_t dense_ws_bytes(const qtam_plan_s* pl, int64_t segs) {
   return align256(layout_for(pl, segs).total) + size_t(segs) * size_t(pl->hp.rows) * size_t(pl->hp.n) * cb;
 }
 
+// Single-tile recovery of row `row`: its N_out-point forward transform in one
+// workgroup, or (rows longer than that) k_fft_cols over that row of each
+// segment into the long-row workspace, then k_tile_rows_rowst.
 template <typename T>
-bool launch_tile_rows(qtam_plan_s* pl, const void* y, void* sx, int row, int64_t segs, hipStream_t st) {
+bool launch_tile_rows(qtam_plan_s* pl, const void* y, void* sx, int row, int64_t segs, char* ws, const WsLayout& lay,
+                      hipStream_t st) {
   using C = typename Complex<T>::type;
   const HostPlan& hp = pl->hp;
   Timed tm(pl, K_INV_ROWS, st);
+  if (pl->big_rows) {
+    const Twiddle2<C> twr{static_cast<const C*>(pl->d_twr_fine), static_cast<const C*>(pl->d_twr_coarse),
+                          pl->twr_bits};
+    const int64_t stride = int64_t(hp.rows) * hp.n_out;   // row `row` of consecutive segments
+    const C* yr = static_cast<const C*>(y) + int64_t(row) * hp.n_out;
+    C* A = reinterpret_cast<C*>(ws + lay.rows) + int64_t(row) * hp.n_out;
+    if (!launch_fft_cols<T, -1>(ilog2(pl->r2), yr, A, pl->r1, segs, stride, pl->d_tw_r2, twr, st, 1)) return false;
+    switch (ilog2(pl->r1)) {
+#define X(LG)                                                                                          \
+  case LG:                                                                                             \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                          \
+      using Geo = ColGeom<T, (1 << LG)>;                                                               \
+      if (pl->r2 % Geo::CC) return false;                                                              \
+      hipLaunchKernelGGL((k_tile_rows_rowst<T, (1 << LG)>), dim3(unsigned(pl->r2 / Geo::CC), unsigned(segs)), \
+                         dim3(Geo::NT), 0, st, A, static_cast<C*>(sx), pl->d_rows,                     \
+                         static_cast<const T*>(pl->d_tab[T_TILE]), row, int(hp.half), stride,          \
+                         int64_t(hp.n_out), pl->r2, static_cast<const C*>(pl->d_tw_r1));               \
+      return true;                                                                                     \
+    }                                                                                                  \
+    return false;
+      QTAM_COL_CASES(X)
+#undef X
+      default: return false;
+    }
+  }
   switch (ilog2(hp.n_out)) {
 #define X(LG)                                                                                          \
   case LG:                                                                                             \
-    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Single32 : kMaxLog2Single64)) {                    \
+    if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Rows32 : kMaxLog2Rows64)) {                        \
       using Geo = RowGeom<T, (1 << LG)>;                                                               \
       hipLaunchKernelGGL((k_tile_rows<T, (1 << LG)>), dim3(unsigned((segs + Geo::G - 1) / Geo::G)),      \
                          dim3(Geo::NT), 0, st, static_cast<const C*>(y), static_cast<C*>(sx), pl->d_rows, \
@@ -1515,9 +1544,7 @@ qtam_status qtam_tile_inverse(qtam_plan_t pl, const void* y, int32_t row, void* 
   if (batch == 0) return QTAM_OK;
   if (!y || !x || !ws) return QTAM_ERR_INVALID_ARG;
   if (!pl->gpu_supported) return pl->unsupported_reason;
-  if (pl->big_rows || pl->bluestein ||
-      ilog2(pl->hp.n_out) > (pl->hp.precision == QTAM_FP64 ? kMaxLog2Single64 : kMaxLog2Single32))
-    return QTAM_ERR_UNSUPPORTED;
+  if (pl->bluestein) return QTAM_ERR_UNSUPPORTED;
   if (!pl->device) return QTAM_ERR_INVALID_ARG;
   const int64_t chunk = std::min<int64_t>(chunk_for(pl, batch, ws_bytes), 65535);
   if (chunk < 1) return QTAM_ERR_WORKSPACE;
@@ -1533,9 +1560,9 @@ qtam_status qtam_tile_inverse(qtam_plan_t pl, const void* y, int32_t row, void* 
     const char* src = static_cast<const char*>(y) + size_t(b0) * size_t(hp.rows) * size_t(hp.n_out) * 2 * rb;
     char* dst = static_cast<char*>(x) + size_t(b0) * size_t(hp.n) * rb;
     void* sx = w + lay.pack;   // [segs][N/2 + 1], within the packed region (R (N/2 + 1) entries per segment)
-    const bool ok = f64 ? (launch_tile_rows<double>(pl, src, sx, row, segs, st) &&
+    const bool ok = f64 ? (launch_tile_rows<double>(pl, src, sx, row, segs, w, lay, st) &&
                            synthesize<double>(pl, sx, hp.half + 1, pl->d_one_start, pl->d_one_rows, dst, segs, w, lay, st))
-                        : (launch_tile_rows<float>(pl, src, sx, row, segs, st) &&
+                        : (launch_tile_rows<float>(pl, src, sx, row, segs, w, lay, st) &&
                            synthesize<float>(pl, sx, hp.half + 1, pl->d_one_start, pl->d_one_rows, dst, segs, w, lay, st));
     if (!ok) return QTAM_ERR_UNSUPPORTED;
     if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");

@@ -38,7 +38,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_tile_rows(
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, -1, TW_MIXED>;
-  __shared__ C lds[Geo::G * lds_size(L)];
+  __shared__ C lds[Geo::G * fft_lds_elems<T, L>()];
   const int t = threadIdx.x, g = t / Geo::TPR, tl = t % Geo::TPR;
   const int seg = static_cast<int>(blockIdx.x) * Geo::G + g;
   const bool ok = seg < segs;
@@ -46,7 +46,7 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_tile_rows(
   C v[Geo::E];
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) v[i] = bload<C>(ry, static_cast<uint32_t>(tl + F::in_off(i)) * sizeof(C));
-  F::run(v, lds + g * lds_size(L), tl, F::twiddles(tw));
+  F::run(v, lds + g * fft_lds_elems<T, L>(), tl, F::twiddles(tw));
   if (!ok) return;
   const RowMeta rm = rows[row];
   C* dst = Sx + int64_t(seg) * (half + 1);
@@ -619,6 +619,46 @@ __global__ __launch_bounds__((ColGeom<T, L1>::NT)) void k_inv_rows_rowst(
   const int64_t seg = gr / R;
   const RowMeta rm = rows[int(gr - seg * R)];
   C* dst = Sbuf + seg * sum_len + rm.off - rm.lo;
+  const T* tb = tab + rm.off - rm.lo;
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) {
+    const int64_t m = k2_0 + cc + l2 * F::out_index(tl, i);
+    const int64_t c = rm.lo + ((m + rm.s - rm.lo) & (n_out - 1));   // kept bin of slot m, if <= hi
+    if (c <= rm.hi) {
+      const T w = tb[c];
+      dst[c] = C{v[i].x * w, v[i].y * w};
+    }
+  }
+}
+
+// Single-tile recovery on rows longer than one workgroup: the second pass of
+// the row's N_out-point forward transform (after k_fft_cols over row `row` of
+// each segment, intermediate rows of stride a_stride), then the kept slots
+// times the tile table into Sx[seg][c], as k_tile_rows does.
+template <typename T, int L1>
+__global__ __launch_bounds__((ColGeom<T, L1>::NT)) void k_tile_rows_rowst(
+    const typename Complex<T>::type* __restrict__ A, typename Complex<T>::type* __restrict__ Sx,
+    const RowMeta* __restrict__ rows, const T* __restrict__ tab, int row, int half, int64_t a_stride,
+    int64_t n_out, int64_t l2, const typename Complex<T>::type* __restrict__ tw) {
+  using C = typename Complex<T>::type;
+  using Geo = ColGeom<T, L1>;
+  using F = BlockFft<T, L1, Geo::E, -1>;
+  __shared__ C lds[Geo::CC * lds_size(L1)];
+  const int t = threadIdx.x;
+  const int64_t seg = blockIdx.y;
+  const int64_t k2_0 = int64_t(blockIdx.x) * Geo::CC;
+  const C* src = A + seg * a_stride + k2_0 * L1;
+  for (int i = t; i < Geo::CC * L1; i += Geo::NT) lds[(i / L1) * lds_size(L1) + lds_pad(i % L1)] = src[i];
+  __syncthreads();
+  const int cc = t % Geo::CC, tl = t / Geo::CC;
+  C* reg = lds + cc * lds_size(L1);
+  C v[Geo::E];
+#pragma unroll
+  for (int i = 0; i < Geo::E; ++i) v[i] = reg[lds_pad(F::in_index(tl, i))];
+  __syncthreads();
+  F::run(v, reg, tl, F::twiddles(tw));
+  const RowMeta rm = rows[row];
+  C* dst = Sx + seg * (half + 1);
   const T* tb = tab + rm.off - rm.lo;
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) {

@@ -37,11 +37,12 @@ def rel_rows(a, b):
 
 
 # (fs, N, N_out): N a power of two (N_out = N), the 6 s x 4096 Hz segment
-# (N/2 = 3 * 4096, N_out = 16384 < N) and N/2 = 5 * 512 (N_out = 4096 < N).
+# (N/2 = 3 * 4096, N_out = 16384 < N), N/2 = 5 * 512 (N_out = 4096 < N) and
+# N/2 = 3 * 8192 (N_out = 32768 < N).
 # With N_out < N a row's band 0..N/2 reaches beyond N_out/2 on one side of
 # its centre for most rows, and only the wrap of slots (c - s) mod N_out
 # places those bins.
-SIZES = [(1024.0, 4096, 4096), (4096.0, 24576, 16384), (1024.0, 5120, 4096)]
+SIZES = [(1024.0, 4096, 4096), (4096.0, 24576, 16384), (1024.0, 5120, 4096), (4096.0, 49152, 32768)]
 
 
 @pytest.mark.parametrize("fs,n,n_out", SIZES)
@@ -71,12 +72,8 @@ def test_regularised_forward_inverse_and_single_tile(torch_dev, precision, fs, n
     Ych = Yc.cpu().numpy().astype(np.complex128)
     assert rel_rows(gp.inverse(Yc).cpu().numpy(), op.inverse(Ych)).max() <= TOL[precision]
     bar = 2000.0 * UNIT[precision] / eps
-    if precision == "fp64" and n_out > 8192:
-        # one-workgroup single-tile rows only (FP64: up to 8192 points)
-        with pytest.raises(qt.QtamError) as e:
-            gp.tile_inverse(Yc, 0)
-        assert e.value.status == 2
-        return
+    # rows of 16384 (FP64) and 32768 points take the two-pass transforms
+    # (FP32 32768: one workgroup exchanging through half the row in LDS)
     for k in (0, R // 2, R - 1):
         xt = gp.tile_inverse(Yc, k).cpu().numpy()
         assert rel_rows(xt, op.tile_inverse(Ych, k)).max() <= bar, k
