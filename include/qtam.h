@@ -218,6 +218,31 @@ size_t qtam_dense_workspace_size(qtam_plan_t plan, int64_t batch);
 qtam_status qtam_dense(qtam_plan_t plan, const void* y, void* dense, int64_t batch,
                        void* ws, size_t ws_bytes, qtam_stream_t stream);
 
+/* Gain x soft-threshold mask on envelope coefficients, the denoising model
+ * of a differentiable pipeline (masking complex coefficients before the
+ * inverse, Sec. V; the transform inside a differentiable denoiser, App. A):
+ *   out[b,k,m] = gain[k] * max(0, 1 - lambda[k] / |y[b,k,m]|) * y[b,k,m],
+ * |y| floored at the smallest normal number. y, out [batch, R, N_out]
+ * complex and gain, lambda [R] real, in the plan's precision, on the plan's
+ * device; out may alias y. Elementwise, one launch per 65535/R segments.
+ * batch = 0 does nothing (y and out may then be NULL).                      */
+qtam_status qtam_mask_forward(qtam_plan_t plan, const void* y, const void* gain, const void* lambda, void* out,
+                              int64_t batch, qtam_stream_t stream);
+
+/* Its gradients: with gout = dL/dout as dL/dRe + i dL/dIm and
+ * p = Re(conj(y) gout),
+ *   gy = gain[k] * (m gout + [m > 0, lambda[k] > 0] (lambda/|y|)(p/|y|)/|y| * y),
+ *   dgain[k] = sum over b and m of m p (rows summed by a fixed tree, then
+ *              the segments in order: identical bits run to run).
+ * gy [batch, R, N_out] complex, dgain [R] real; ws holds the rows' partial
+ * sums: at least qtam_mask_workspace_size(plan, batch) bytes
+ * (QTAM_ERR_WORKSPACE otherwise). batch = 0 sets dgain to 0; y, gout, gy
+ * and ws may then be NULL. NULL gain, lambda or dgain: QTAM_ERR_INVALID_ARG. */
+size_t qtam_mask_workspace_size(qtam_plan_t plan, int64_t batch);
+qtam_status qtam_mask_backward(qtam_plan_t plan, const void* y, const void* gain, const void* lambda,
+                               const void* gout, void* gy, void* dgain, int64_t batch, void* ws,
+                               size_t ws_bytes, qtam_stream_t stream);
+
 /* Forward transform of one batch under several plans at once (the multi-Q
  * extension of App. A, where every configuration of the bank works from the
  * same spectrum): the real spectrum of each segment is computed once and

@@ -63,49 +63,31 @@ class QTAM(torch.nn.Module):
 
 class SoftThresholdGainFn(torch.autograd.Function):
     """Y' = g_k * m * Y with m = max(0, 1 - lambda_k / |Y|) on row k (the row
-    axis is the second to last of Y), with its gradient written out rather
-    than assembled by autograd from one elementwise launch per operation.
-    With G the incoming gradient (dL/dRe + i dL/dIm) and p = Re(conj(Y) G):
+    axis is the second to last of Y), forward and gradient both in the
+    library's mask kernels (qtam_mask_forward / qtam_mask_backward). With G
+    the incoming gradient (dL/dRe + i dL/dIm) and p = Re(conj(Y) G):
         dY = g_k * (m G + [|Y| > lambda_k] * lambda_k p / |Y|^3 * Y),
         dg_k = sum over every other axis of m p;
-    where |Y| <= lambda_k the mask is zero and locally constant, so dY = 0."""
+    where |Y| <= lambda_k the mask is zero and locally constant, so dY = 0.
+    The thresholds get no gradient."""
 
     @staticmethod
-    def forward(ctx, y: torch.Tensor, gain: torch.Tensor, thresholds: torch.Tensor) -> torch.Tensor:
-        y = y.resolve_conj()
-        yr = torch.view_as_real(y)
-        r = y.abs().clamp_min_(torch.finfo(yr.dtype).tiny)
-        lam = thresholds[:, None]
-        one = torch.ones((), dtype=r.dtype, device=r.device)
-        m = torch.addcdiv(one, lam, r, value=-1.0).clamp_min_(0.0)
-        out = torch.view_as_complex(yr * (m * gain[:, None])[..., None])
-        ctx.save_for_backward(y, gain, thresholds, r, m)
-        return out
+    def forward(ctx, y: torch.Tensor, gain: torch.Tensor, thresholds: torch.Tensor, plan: Plan) -> torch.Tensor:
+        y = y.resolve_conj().contiguous()
+        ctx.plan = plan
+        ctx.save_for_backward(y, gain, thresholds)
+        return plan.mask_forward(y, gain.contiguous(), thresholds.contiguous())
 
     @staticmethod
     def backward(ctx, gout: torch.Tensor):
-        y, gain, thresholds, r, m = ctx.saved_tensors
-        yr = torch.view_as_real(y)
-        gr = torch.view_as_real(gout.resolve_conj())
-        p = (yr * gr).sum(-1)
-        gy = gg = None
-        if ctx.needs_input_grad[0]:
-            lam = thresholds[:, None]
-            # lambda p / |Y|^3 as (lambda/|Y|)(p/|Y|)/|Y|: where m > 0 and
-            # lambda > 0, |Y| > lambda and |p| <= |Y| |G|, so no factor
-            # overflows or underflows to 0/0; a zero threshold adds nothing
-            c = torch.where((m > 0) & (lam > 0), (lam / r) * (p / r) / r,
-                            torch.zeros((), dtype=p.dtype, device=p.device))
-            g = gain[:, None]
-            gy = torch.view_as_complex(torch.addcmul(gr * (m * g)[..., None], yr, (c * g)[..., None]))
-        if ctx.needs_input_grad[1]:
-            dims = [d for d in range(p.dim()) if d != p.dim() - 2]
-            gg = (m * p).sum(dim=dims)
-        return gy, gg, None
+        y, gain, thresholds = ctx.saved_tensors
+        gy, gg = ctx.plan.mask_backward(y, gain.contiguous(), thresholds.contiguous(),
+                                        gout.resolve_conj().contiguous())
+        return (gy if ctx.needs_input_grad[0] else None), (gg if ctx.needs_input_grad[1] else None), None, None
 
 
-def soft_threshold_gain(y: torch.Tensor, gain: torch.Tensor, thresholds: torch.Tensor) -> torch.Tensor:
-    return SoftThresholdGainFn.apply(y, gain, thresholds)
+def soft_threshold_gain(y: torch.Tensor, gain: torch.Tensor, thresholds: torch.Tensor, plan: Plan) -> torch.Tensor:
+    return SoftThresholdGainFn.apply(y, gain, thresholds, plan)
 
 
 class GainThresholdDenoiser(torch.nn.Module):
@@ -123,4 +105,4 @@ class GainThresholdDenoiser(torch.nn.Module):
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
         Y = self.qtam(x)
-        return self.qtam.inverse(soft_threshold_gain(Y, self.gain, self.thresholds))
+        return self.qtam.inverse(soft_threshold_gain(Y, self.gain, self.thresholds, self.qtam.plan))

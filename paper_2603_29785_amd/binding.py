@@ -97,7 +97,8 @@ EXPORTED = [
     "qtam_forward", "qtam_inverse", "qtam_forward_adjoint", "qtam_inverse_adjoint",
     "qtam_forward_metric", "qtam_select_planes", "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string",
     "qtam_dense", "qtam_dense_workspace_size", "qtam_tile_inverse", "qtam_last_error", "qtam_version",
-    "qtam_forward_sweep", "qtam_forward_noalloc",
+    "qtam_forward_sweep", "qtam_forward_noalloc", "qtam_mask_forward", "qtam_mask_backward",
+    "qtam_mask_workspace_size",
 ]
 
 
@@ -122,6 +123,12 @@ def _load():
         f = getattr(L, name)
         f.argtypes = [vp, vp, vp, i64, vp, sz, vp]
         f.restype = ctypes.c_int
+    L.qtam_mask_forward.argtypes = [vp, vp, vp, vp, vp, i64, vp]
+    L.qtam_mask_forward.restype = ctypes.c_int
+    L.qtam_mask_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp, sz, vp]
+    L.qtam_mask_backward.restype = ctypes.c_int
+    L.qtam_mask_workspace_size.argtypes = [vp, i64]
+    L.qtam_mask_workspace_size.restype = sz
     L.qtam_forward_noalloc.argtypes = [vp, vp, vp, i64, vp]
     L.qtam_forward_noalloc.restype = ctypes.c_int
     L.qtam_tile_inverse.argtypes = [vp, vp, ctypes.c_int32, vp, i64, vp, sz, vp]
@@ -414,6 +421,57 @@ class Plan:
         _check(lib.qtam_forward_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                         int(batch), ctypes.c_void_p(stream.cuda_stream)), "qtam_forward_noalloc")
         return y
+
+    def _check_row_params(self, t, what, device):
+        torch = self._torch()
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.device == device):
+            raise TypeError("%s: expected a CUDA (HIP) tensor on %s" % (what, device))
+        if t.dtype != self._real_dtype() or tuple(t.shape) != (self.R,):
+            raise ValueError("%s: expected real %s [%d], got %s %s" % (what, self._real_dtype(), self.R, t.dtype,
+                                                                     tuple(t.shape)))
+        return t.contiguous()
+
+    def mask_forward(self, y, gain, thresholds, out=None, stream=None):
+        """gain[k] * max(0, 1 - thresholds[k] / |y|) * y on envelopes
+        [..., R, N_out] (qtam_mask_forward)."""
+        torch = self._torch()
+        y = self._check_rows(y)
+        gain = self._check_row_params(gain, "gain", y.device)
+        thresholds = self._check_row_params(thresholds, "thresholds", y.device)
+        lead = y.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        o = self._out(out, tuple(y.shape), self._complex_dtype(), y.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(y.device)
+        _check(lib.qtam_mask_forward(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(gain.data_ptr()),
+                                     ctypes.c_void_p(thresholds.data_ptr()), ctypes.c_void_p(o.data_ptr()),
+                                     int(batch), ctypes.c_void_p(stream.cuda_stream)), "qtam_mask_forward")
+        return o
+
+    def mask_backward(self, y, gain, thresholds, gout, stream=None):
+        """(dL/dy, dL/dgain) of mask_forward given gout = dL/dout
+        (qtam_mask_backward)."""
+        torch = self._torch()
+        y = self._check_rows(y)
+        gout = self._check_rows(gout)
+        if gout.shape != y.shape or gout.device != y.device:
+            raise ValueError("gout must match y: %s vs %s" % (tuple(gout.shape), tuple(y.shape)))
+        gain = self._check_row_params(gain, "gain", y.device)
+        thresholds = self._check_row_params(thresholds, "thresholds", y.device)
+        lead = y.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        gy = torch.empty_like(y)
+        dgain = torch.empty(self.R, dtype=self._real_dtype(), device=y.device)
+        wsb = max(int(lib.qtam_mask_workspace_size(self._h, int(batch))), 1)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=y.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(y.device)
+        _check(lib.qtam_mask_backward(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(gain.data_ptr()),
+                                      ctypes.c_void_p(thresholds.data_ptr()), ctypes.c_void_p(gout.data_ptr()),
+                                      ctypes.c_void_p(gy.data_ptr()), ctypes.c_void_p(dgain.data_ptr()),
+                                      int(batch), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(wsb),
+                                      ctypes.c_void_p(stream.cuda_stream)), "qtam_mask_backward")
+        return gy, dgain
 
     def forward_metric(self, x, out=None, metric=None, ws=None, stream=None):
         """Forward plus per-row statistics: (Y, metric) with metric [..., R]

@@ -35,6 +35,7 @@
 #include <new>
 #include <vector>
 
+#include "mask_kernels.hpp"
 #include "ola_kernels.hpp"
 #include "plan.hpp"
 #include "qtam.h"
@@ -51,14 +52,15 @@ namespace {
 enum Kind { K_SPEC = 0, K_SPEC1, K_SPEC2, K_TWIST, K_FWD_ROWS, K_FWD_ROWS2, K_INV_ROWS, K_INV_ROWS2, K_OLA,
             K_SYN, K_SYN1, K_SYN2, K_ROW_STATS, K_PLANE_BEST, K_GATHER, K_SPEC_PERM, K_SPEC_RADIX, K_SYN_RADIX,
             K_SYN_PERM, K_DENSE_PLACE, K_DENSE_FFT, K_DENSE_FFT1, K_DENSE_FFT2, K_DENSE_RADIX, K_DENSE_PERM,
-            K_NUM };
+            K_MASK_FWD, K_MASK_BWD, K_NUM };
 const char* const kKindName[K_NUM] = {"spectrum_fft", "spectrum_fft_pass1", "spectrum_fft_pass2",
                                        "spectrum_twist", "fwd_rows", "fwd_rows_pass2", "inv_rows",
                                        "inv_rows_pass2", "overlap_add", "synthesis_fft",
                                        "synthesis_fft_pass1", "synthesis_fft_pass2", "row_stats",
                                        "plane_best", "gather_plane", "spectrum_permute", "spectrum_radix",
                                        "synthesis_radix", "synthesis_permute", "dense_place", "dense_fft",
-                                       "dense_fft_pass1", "dense_fft_pass2", "dense_radix", "dense_permute"};
+                                       "dense_fft_pass1", "dense_fft_pass2", "dense_radix", "dense_permute",
+                                       "mask_forward", "mask_backward"};
 
 enum Table { T_FWD = 0, T_DUAL = 1, T_AFWD = 2, T_AINV = 3, T_DENSE = 4, T_TILE = 5 };
 
@@ -1567,6 +1569,80 @@ qtam_status qtam_tile_inverse(qtam_plan_t pl, const void* y, int32_t row, void* 
     if (!ok) return QTAM_ERR_UNSUPPORTED;
     if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
   }
+  return QTAM_OK;
+}
+
+size_t qtam_mask_workspace_size(qtam_plan_t pl, int64_t batch) {
+  if (!pl || batch < 1) return 0;
+  return size_t(batch) * size_t(pl->hp.rows) * (pl->hp.precision == QTAM_FP64 ? 8 : 4);
+}
+
+qtam_status qtam_mask_forward(qtam_plan_t pl, const void* y, const void* gain, const void* lambda, void* out,
+                              int64_t batch, qtam_stream_t stream) {
+  if (!pl || batch < 0) return QTAM_ERR_INVALID_ARG;
+  if (batch == 0) return QTAM_OK;
+  if (!y || !gain || !lambda || !out || !pl->device) return QTAM_ERR_INVALID_ARG;
+  const HostPlan& hp = pl->hp;
+  const bool f64 = hp.precision == QTAM_FP64;
+  const size_t cb = f64 ? 16 : 8;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t chunk = std::max<int64_t>(1, 65535 / hp.rows);   // rows of a chunk index grid.y
+  (void)hipGetLastError();
+  for (int64_t b0 = 0; b0 < batch; b0 += chunk) {
+    const int64_t segs = std::min(chunk, batch - b0);
+    const size_t off = size_t(b0) * size_t(hp.rows) * size_t(hp.n_out) * cb;
+    const dim3 grid(unsigned((hp.n_out + 255) / 256), unsigned(segs * hp.rows));
+    Timed tm(pl, K_MASK_FWD, st);
+    if (f64)
+      hipLaunchKernelGGL((k_mask_fwd<double>), grid, dim3(256), 0, st,
+                         reinterpret_cast<const double2*>(static_cast<const char*>(y) + off),
+                         static_cast<const double*>(gain), static_cast<const double*>(lambda),
+                         reinterpret_cast<double2*>(static_cast<char*>(out) + off), hp.rows, hp.n_out);
+    else
+      hipLaunchKernelGGL((k_mask_fwd<float>), grid, dim3(256), 0, st,
+                         reinterpret_cast<const float2*>(static_cast<const char*>(y) + off),
+                         static_cast<const float*>(gain), static_cast<const float*>(lambda),
+                         reinterpret_cast<float2*>(static_cast<char*>(out) + off), hp.rows, hp.n_out);
+  }
+  if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
+  return QTAM_OK;
+}
+
+qtam_status qtam_mask_backward(qtam_plan_t pl, const void* y, const void* gain, const void* lambda, const void* gout,
+                               void* gy, void* dgain, int64_t batch, void* ws, size_t ws_bytes,
+                               qtam_stream_t stream) {
+  if (!pl || batch < 0) return QTAM_ERR_INVALID_ARG;
+  if (!gain || !lambda || !dgain || !pl->device) return QTAM_ERR_INVALID_ARG;
+  if (batch > 0 && (!y || !gout || !gy || !ws)) return QTAM_ERR_INVALID_ARG;
+  const HostPlan& hp = pl->hp;
+  const bool f64 = hp.precision == QTAM_FP64;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  if (batch > 0) {
+    if (ws_bytes < qtam_mask_workspace_size(pl, batch)) return QTAM_ERR_WORKSPACE;
+    if (batch * int64_t(hp.rows) > int64_t(0x7fffffff)) return QTAM_ERR_INVALID_ARG;   // rows index grid.x
+    Timed tm(pl, K_MASK_BWD, st);
+    const dim3 grid(unsigned(batch * hp.rows));
+    if (f64)
+      hipLaunchKernelGGL((k_mask_bwd<double>), grid, dim3(256), 0, st, static_cast<const double2*>(y),
+                         static_cast<const double2*>(gout), static_cast<const double*>(gain),
+                         static_cast<const double*>(lambda), static_cast<double2*>(gy), static_cast<double*>(ws),
+                         hp.rows, hp.n_out);
+    else
+      hipLaunchKernelGGL((k_mask_bwd<float>), grid, dim3(256), 0, st, static_cast<const float2*>(y),
+                         static_cast<const float2*>(gout), static_cast<const float*>(gain),
+                         static_cast<const float*>(lambda), static_cast<float2*>(gy), static_cast<float*>(ws),
+                         hp.rows, hp.n_out);
+  }
+  // the gain gradient: the rows' partial sums added over the segments in order (0 for an empty batch)
+  const dim3 g2(unsigned((hp.rows + 255) / 256));
+  if (f64)
+    hipLaunchKernelGGL((k_gain_sum<double>), g2, dim3(256), 0, st, static_cast<const double*>(ws),
+                       static_cast<double*>(dgain), hp.rows, batch);
+  else
+    hipLaunchKernelGGL((k_gain_sum<float>), g2, dim3(256), 0, st, static_cast<const float*>(ws),
+                       static_cast<float*>(dgain), hp.rows, batch);
+  if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
   return QTAM_OK;
 }
 

@@ -1,11 +1,12 @@
-"""The denoiser's soft-threshold gain with its hand-written gradient, on CPU
-tensors (it is plain torch arithmetic, no kernels of the library): gradcheck in
-FP64, and values and gradients equal to autograd through the elementwise
-composition Y * (g * max(0, 1 - lambda / max(|Y|, tiny)))."""
+"""The reference of the denoiser's soft-threshold gain with its hand-written
+gradient (tests/mask_reference.py, the formula the library's mask kernels
+implement), on CPU tensors: gradcheck in FP64, and values and gradients equal
+to autograd through the elementwise composition
+Y * (g * max(0, 1 - lambda / max(|Y|, tiny)))."""
 import pytest
 import torch
 
-from paper_2603_29785_amd.autograd import soft_threshold_gain
+from mask_reference import reference_soft_threshold_gain as soft_threshold_gain
 
 
 def composed(y, gain, lam):
