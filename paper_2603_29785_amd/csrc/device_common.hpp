@@ -67,13 +67,16 @@ struct RowGeom {
 // EP > 0 sets the values per thread (the second four-step pass of the
 // spectrum and synthesis transforms runs faster with 8 in FP32: twice the
 // waves per workgroup for its LDS-staged rows).
-template <typename T, int L, int EP = 0>
+template <typename T, int L, int EP = 0, int CW = 0>
 struct ColGeom {
   static constexpr int E0 = EP > 0 ? EP : elems_per_thread<T>();
   static constexpr int E = L < E0 ? L : E0;
   static constexpr int TPR = L / E;
   static constexpr int CAP = (65536 / (2 * int(sizeof(T)))) / L;
-  static constexpr int CC = CAP >= 16 ? 16 : (CAP >= 4 ? CAP : 4);
+  // CW > 0 asks for CW columns where their LDS (with its padding) fits in
+  // 144 KiB and CW * TPR threads make one workgroup
+  static constexpr bool WIDE = CW > 0 && CW * (L + L / 32) * 2 * int(sizeof(T)) <= 147456 && CW * TPR <= 1024;
+  static constexpr int CC = WIDE ? CW : (CAP >= 16 ? 16 : (CAP >= 4 ? CAP : 4));
   static constexpr int NT = CC * TPR;
 };
 

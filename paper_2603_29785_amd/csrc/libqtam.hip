@@ -73,6 +73,15 @@ constexpr int kMaxLog2Rows64 = 13;
 // Values per thread of the second four-step pass of the spectrum and
 // synthesis transforms (its twiddle table, d_tw_n1, is built for it).
 constexpr int kPass2E = 8;
+// Columns per workgroup of the first four-step pass, and rows per workgroup
+// of the second, where the LDS and the 1024-thread limit allow it (else 16):
+// longer contiguous runs per access. Measured: 32 columns faster than 16 in
+// the first pass of the spectrum and synthesis transforms, 64 slower; 32
+// rows faster in the spectrum's fused twist pass and the row passes with
+// sixteen (FP32) or eight (FP64) values per thread, slower in the synthesis
+// second pass with eight values per thread in FP32, which keeps 16.
+constexpr int kColWide = 32;
+constexpr int kRowWide = 32;
 
 int ilog2(int64_t v) {
   int l = 0;
@@ -499,6 +508,13 @@ bool launch_fft_cols(int log2l, const void* in, void* out, int64_t n1, int64_t s
 #define X(LG)                                                                                     \
   case LG:                                                                                        \
     if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                     \
+      using GeoW = ColGeom<T, (1 << LG), 0, kColWide>;                                            \
+      if (n1 % GeoW::CC == 0) {                                                                   \
+        hipLaunchKernelGGL((k_fft_cols<T, (1 << LG), S, kColWide>), dim3(unsigned(n1 / GeoW::CC), unsigned(segs)), \
+                           dim3(GeoW::NT), 0, st, static_cast<const C*>(in), static_cast<C*>(out), n1, \
+                           seg_stride, static_cast<const C*>(tw), tw2, tw_mul);                   \
+        return true;                                                                              \
+      }                                                                                           \
       using Geo = ColGeom<T, (1 << LG)>;                                                          \
       if (n1 % Geo::CC) return false;                                                             \
       hipLaunchKernelGGL((k_fft_cols<T, (1 << LG), S>), dim3(unsigned(n1 / Geo::CC), unsigned(segs)), \
@@ -521,6 +537,14 @@ bool launch_fft_rows_t(int log2l, const void* in, void* out, int64_t n2, int64_t
 #define X(LG)                                                                                       \
   case LG:                                                                                          \
     if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                       \
+      constexpr int CW = EP == 0 ? kRowWide : 0;                                                    \
+      using GeoW = ColGeom<T, (1 << LG), EP, CW>;                                                   \
+      if (n2 % GeoW::CC == 0) {                                                                     \
+        hipLaunchKernelGGL((k_fft_rows_t<T, (1 << LG), S, EP, CW>), dim3(unsigned(n2 / GeoW::CC), unsigned(segs)), \
+                           dim3(GeoW::NT), 0, st, static_cast<const C*>(in), static_cast<C*>(out), n2, \
+                           seg_stride, static_cast<const C*>(tw));                                  \
+        return true;                                                                                \
+      }                                                                                             \
       using Geo = ColGeom<T, (1 << LG), EP>;                                                        \
       if (n2 % Geo::CC) return false;                                                               \
       hipLaunchKernelGGL((k_fft_rows_t<T, (1 << LG), S, EP>), dim3(unsigned(n2 / Geo::CC), unsigned(segs)), \
@@ -543,6 +567,13 @@ bool launch_spec_rows_twist(int log2l, const void* in, void* out, int64_t n2, in
 #define X(LG)                                                                                       \
   case LG:                                                                                          \
     if constexpr ((LG) <= (sizeof(T) == 4 ? kMaxLog2Col32 : kMaxLog2Col64)) {                       \
+      using GeoW = ColGeom<T, (1 << LG), kPass2E, kRowWide>;                                        \
+      if (n2 % GeoW::CC == 0) {                                                                     \
+        hipLaunchKernelGGL((k_spec_rows_twist<T, (1 << LG), kPass2E, kRowWide>), dim3(unsigned(n2 / GeoW::CC), unsigned(segs)), \
+                           dim3(GeoW::NT), 0, st, static_cast<const C*>(in), static_cast<C*>(out), n2, \
+                           seg_stride, static_cast<const C*>(tw), tw2);                             \
+        return true;                                                                                \
+      }                                                                                             \
       using Geo = ColGeom<T, (1 << LG), kPass2E>;                                                   \
       if (n2 % Geo::CC) return false;                                                               \
       hipLaunchKernelGGL((k_spec_rows_twist<T, (1 << LG), kPass2E>), dim3(unsigned(n2 / Geo::CC), unsigned(segs)), \

@@ -41,13 +41,13 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fft_rows(
 // view (element stride N1), times exp(S 2 pi i n1 k2 / M), written back in
 // place-order. CC adjacent columns per workgroup, column index fastest
 // across threads so every access is a contiguous run of CC values.
-template <typename T, int L, int S>
-__global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_cols(
+template <typename T, int L, int S, int CW = 0>
+__global__ __launch_bounds__((ColGeom<T, L, 0, CW>::NT)) void k_fft_cols(
     const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
     int64_t n1_count, int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw,
     Twiddle2<typename Complex<T>::type> tw2, int tw_mul) {
   using C = typename Complex<T>::type;
-  using Geo = ColGeom<T, L>;
+  using Geo = ColGeom<T, L, 0, CW>;
   using F = BlockFft<T, L, Geo::E, S>;
   __shared__ C lds[Geo::CC * lds_size(L)];
   const int t = threadIdx.x, c = t % Geo::CC, tl = t / Geo::CC;
@@ -70,12 +70,12 @@ __global__ __launch_bounds__((ColGeom<T, L>::NT)) void k_fft_cols(
 // Four-step, second pass: length-N1 FFTs along the contiguous rows k2 of the
 // intermediate; CC rows per workgroup are staged through LDS with a linear
 // (coalesced) load, results go to Z[k2 + N2 k1] in runs of CC values.
-template <typename T, int L, int S, int EP = 0>
-__global__ __launch_bounds__((ColGeom<T, L, EP>::NT)) void k_fft_rows_t(
+template <typename T, int L, int S, int EP = 0, int CW = 0>
+__global__ __launch_bounds__((ColGeom<T, L, EP, CW>::NT)) void k_fft_rows_t(
     const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out,
     int64_t n2_count, int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw) {
   using C = typename Complex<T>::type;
-  using Geo = ColGeom<T, L, EP>;
+  using Geo = ColGeom<T, L, EP, CW>;
   using F = BlockFft<T, L, Geo::E, S>;
   __shared__ C lds[Geo::CC * lds_size(L)];
   const int t = threadIdx.x;
@@ -102,12 +102,12 @@ __global__ __launch_bounds__((ColGeom<T, L, EP>::NT)) void k_fft_rows_t(
 // mirrors N2 - j H - c (workgroup 0: rows 0 .. H-1, N2/2 and N2-H+1 .. N2-1,
 // rows 0 and N2/2 being their own mirrors). After the row transforms the
 // values go through LDS to the thread that twists each bin.
-template <typename T, int L, int EP = 0>
-__global__ __launch_bounds__((ColGeom<T, L, EP>::NT)) void k_spec_rows_twist(
+template <typename T, int L, int EP = 0, int CW = 0>
+__global__ __launch_bounds__((ColGeom<T, L, EP, CW>::NT)) void k_spec_rows_twist(
     const typename Complex<T>::type* __restrict__ in, typename Complex<T>::type* __restrict__ out, int64_t n2,
     int64_t seg_stride, const typename Complex<T>::type* __restrict__ tw, Twiddle2<typename Complex<T>::type> tw2) {
   using C = typename Complex<T>::type;
-  using Geo = ColGeom<T, L, EP>;
+  using Geo = ColGeom<T, L, EP, CW>;
   using F = BlockFft<T, L, Geo::E, -1>;
   constexpr int CC = Geo::CC, H = CC / 2;
   static_assert(CC % 2 == 0, "paired rows");
