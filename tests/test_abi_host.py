@@ -342,3 +342,28 @@ def test_plan_host_allocation_failure_is_oom():
     assert e.value.status == binding.QTAM_ERR_OOM
     assert "host memory" in binding.lib.qtam_last_error().decode()
     assert host_plan(sample_rate=4096.0, n_samples=16384, q=8.0, f_min=20.0, f_max=1000.0, n_rows=64).R == 64
+
+
+@pytest.mark.parametrize("precision,b", [("fp32", 4), ("fp64", 8)])
+def test_mask_entry_points_validate_without_device(precision, b):
+    """The denoiser's mask calls: workspace of one real per (segment, row);
+    argument checks before any device work (a plan without device tables,
+    NULL buffers, negative batches); an empty forward batch is a no-op."""
+    gp = host_plan(sample_rate=4096.0, n_samples=32768, q=8.0, f_min=20.0, f_max=2000.0, n_rows=128,
+                   precision=precision)
+    L = binding.lib
+    assert L.qtam_mask_workspace_size(gp._h, 64) == 64 * 128 * b
+    assert L.qtam_mask_workspace_size(gp._h, 0) == 0
+    assert L.qtam_mask_workspace_size(None, 4) == 0
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: the calls fail validation first
+    ws = L.qtam_mask_workspace_size(gp._h, 2)
+    inv = binding.QTAM_ERR_INVALID_ARG
+    assert L.qtam_mask_forward(gp._h, dummy, dummy, dummy, dummy, 0, None) == binding.QTAM_OK
+    assert L.qtam_mask_forward(gp._h, dummy, dummy, dummy, dummy, 2, None) == inv      # no device tables
+    assert L.qtam_mask_forward(gp._h, dummy, dummy, dummy, dummy, -1, None) == inv
+    assert L.qtam_mask_forward(None, dummy, dummy, dummy, dummy, 2, None) == inv
+    args = (dummy, dummy, dummy, dummy, dummy, dummy)
+    assert L.qtam_mask_backward(gp._h, *args, 2, dummy, ws, None) == inv               # no device tables
+    assert L.qtam_mask_backward(gp._h, *args, -1, dummy, ws, None) == inv
+    assert L.qtam_mask_backward(None, *args, 2, dummy, ws, None) == inv
+    assert L.qtam_mask_backward(gp._h, dummy, None, dummy, dummy, dummy, dummy, 0, None, 0, None) == inv
