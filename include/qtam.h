@@ -232,8 +232,9 @@ qtam_status qtam_mask_forward(qtam_plan_t plan, const void* y, const void* gain,
 /* Its gradients: with gout = dL/dout as dL/dRe + i dL/dIm and
  * p = Re(conj(y) gout),
  *   gy = gain[k] * (m gout + [m > 0, lambda[k] > 0] (lambda/|y|)(p/|y|)/|y| * y),
- *   dgain[k] = sum over b and m of m p (rows summed by a fixed tree, then
- *              the segments in order: identical bits run to run).
+ *   dgain[k] = sum over b and m of m p (each row by a fixed tree, then the
+ *              segments by fixed lane strides and a fixed butterfly:
+ *              identical bits run to run).
  * gy [batch, R, N_out] complex, dgain [R] real; ws holds the rows' partial
  * sums: at least qtam_mask_workspace_size(plan, batch) bytes
  * (QTAM_ERR_WORKSPACE otherwise). batch = 0 sets dgain to 0; y, gout, gy

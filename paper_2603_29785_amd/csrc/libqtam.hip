@@ -1665,13 +1665,14 @@ qtam_status qtam_mask_backward(qtam_plan_t pl, const void* y, const void* gain, 
                          static_cast<const float*>(lambda), static_cast<float2*>(gy), static_cast<float*>(ws),
                          hp.rows, hp.n_out);
   }
-  // the gain gradient: the rows' partial sums added over the segments in order (0 for an empty batch)
-  const dim3 g2(unsigned((hp.rows + 255) / 256));
+  // the gain gradient: the rows' partial sums added over the segments, one
+  // wave per row in a fixed order (0 for an empty batch)
+  const dim3 g2(unsigned(hp.rows));
   if (f64)
-    hipLaunchKernelGGL((k_gain_sum<double>), g2, dim3(256), 0, st, static_cast<const double*>(ws),
+    hipLaunchKernelGGL((k_gain_sum<double>), g2, dim3(64), 0, st, static_cast<const double*>(ws),
                        static_cast<double*>(dgain), hp.rows, batch);
   else
-    hipLaunchKernelGGL((k_gain_sum<float>), g2, dim3(256), 0, st, static_cast<const float*>(ws),
+    hipLaunchKernelGGL((k_gain_sum<float>), g2, dim3(64), 0, st, static_cast<const float*>(ws),
                        static_cast<float*>(dgain), hp.rows, batch);
   if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
   return QTAM_OK;

@@ -78,15 +78,19 @@ __global__ __launch_bounds__(256) void k_mask_bwd(const typename Complex<T>::typ
   if (threadIdx.x == 0) part[gr] = red[0];
 }
 
-// dL/dg_k = sum over segments, in segment order, of part[seg * R + k].
+// dL/dg_k = sum over segments of part[seg * R + k], one wave per k: lane l
+// adds segments l, l + 64, l + 128, ... in that order, then the lanes combine
+// by a fixed xor butterfly (the same order on every call).
 template <typename T>
-__global__ __launch_bounds__(256) void k_gain_sum(const T* __restrict__ part, T* __restrict__ dgain, int R,
-                                                  int64_t segs) {
-  const int k = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
-  if (k >= R) return;
+__global__ __launch_bounds__(64) void k_gain_sum(const T* __restrict__ part, T* __restrict__ dgain, int R,
+                                                 int64_t segs) {
+  const int k = static_cast<int>(blockIdx.x);
+  const int l = static_cast<int>(threadIdx.x);
   T s = 0;
-  for (int64_t b = 0; b < segs; ++b) s += part[b * R + k];
-  dgain[k] = s;
+  for (int64_t b = l; b < segs; b += 64) s += part[b * R + k];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+  if (l == 0) dgain[k] = s;
 }
 
 }  // namespace qtam
