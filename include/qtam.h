@@ -231,7 +231,7 @@ qtam_status qtam_mask_forward(qtam_plan_t plan, const void* y, const void* gain,
 
 /* Its gradients: with gout = dL/dout as dL/dRe + i dL/dIm and
  * p = Re(conj(y) gout),
- *   gy = gain[k] * (m gout + [m > 0, lambda[k] > 0] (lambda/|y|)(p/|y|)/|y| * y),
+ *   gy = gain[k] * (m gout + [m > 0, lambda[k] > 0] (lambda/|y|)(p/|y|^2) * y),
  *   dgain[k] = sum over b and m of m p (each row by a fixed tree, then the
  *              segments by fixed lane strides and a fixed butterfly:
  *              identical bits run to run).
@@ -243,6 +243,33 @@ size_t qtam_mask_workspace_size(qtam_plan_t plan, int64_t batch);
 qtam_status qtam_mask_backward(qtam_plan_t plan, const void* y, const void* gain, const void* lambda,
                                const void* gout, void* gy, void* dgain, int64_t batch, void* ws,
                                size_t ws_bytes, qtam_stream_t stream);
+
+/* The mask fused into the inverse: x = qtam_inverse(mask(y)) with mask as in
+ * qtam_mask_forward, applied to each envelope value as the inverse rows
+ * kernel loads it (the masked envelopes are never written). Same layouts,
+ * workspace and results as qtam_mask_forward followed by qtam_inverse.
+ * Rows transformed in one workgroup only (power-of-two N_out up to 32768
+ * FP32 / 8192 FP64): other plans return QTAM_ERR_UNSUPPORTED before any
+ * launch, also for batch = 0, which otherwise does nothing (a query: NULL
+ * pointers are then accepted).                                              */
+qtam_status qtam_inverse_masked(qtam_plan_t plan, const void* y, const void* gain, const void* lambda,
+                                void* x, int64_t batch, void* ws, size_t ws_bytes, qtam_stream_t stream);
+
+/* Its adjoint, the backward pass of the denoiser's mask and inverse: with gx
+ * = dL/dx [batch, N], gy = dL/dy [batch, R, N_out] and dgain [R] as from
+ * qtam_inverse_adjoint (giving dL/d mask(y)) followed by qtam_mask_backward,
+ * the mask's gradient applied in the rows kernel's epilogue (dL/d mask(y)
+ * is never written). y is the unmasked input of qtam_inverse_masked. ws: at
+ * least qtam_masked_adjoint_workspace_size(plan, batch) bytes (its first
+ * part holds the gain gradient's per-row partial sums; with less, the
+ * transform runs in chunks down to one segment, below that
+ * QTAM_ERR_WORKSPACE). dgain sums fixed trees per row and fixed lane strides
+ * over the segments: identical bits run to run. batch = 0 sets dgain to 0.
+ * Plans as for qtam_inverse_masked.                                          */
+size_t qtam_masked_adjoint_workspace_size(qtam_plan_t plan, int64_t batch);
+qtam_status qtam_inverse_masked_adjoint(qtam_plan_t plan, const void* gx, const void* y, const void* gain,
+                                        const void* lambda, void* gy, void* dgain, int64_t batch, void* ws,
+                                        size_t ws_bytes, qtam_stream_t stream);
 
 /* Forward transform of one batch under several plans at once (the multi-Q
  * extension of App. A, where every configuration of the bank works from the

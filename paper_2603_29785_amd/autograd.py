@@ -90,6 +90,37 @@ def soft_threshold_gain(y: torch.Tensor, gain: torch.Tensor, thresholds: torch.T
     return SoftThresholdGainFn.apply(y, gain, thresholds, plan)
 
 
+class MaskedInverseFn(torch.autograd.Function):
+    """x = inverse(g_k * m * Y), the mask of SoftThresholdGainFn and the
+    inverse transform in one pass (qtam_inverse_masked: the mask is applied
+    as the inverse rows load Y); the backward pass is the inverse adjoint with
+    the mask's gradient in its rows kernel (qtam_inverse_masked_adjoint). The
+    same values and gradients as soft_threshold_gain followed by qtam_inverse,
+    without the masked envelopes or their gradient in memory."""
+
+    @staticmethod
+    def forward(ctx, y: torch.Tensor, gain: torch.Tensor, thresholds: torch.Tensor, plan: Plan) -> torch.Tensor:
+        y = y.resolve_conj().contiguous()
+        gain, thresholds = gain.contiguous(), thresholds.contiguous()
+        ctx.plan = plan
+        ctx.save_for_backward(y, gain, thresholds)
+        return plan.inverse_masked(y, gain, thresholds)
+
+    @staticmethod
+    def backward(ctx, gx: torch.Tensor):
+        y, gain, thresholds = ctx.saved_tensors
+        gy, gg = ctx.plan.inverse_masked_adjoint(gx.contiguous(), y, gain, thresholds)
+        return (gy if ctx.needs_input_grad[0] else None), (gg if ctx.needs_input_grad[1] else None), None, None
+
+
+def masked_inverse(y: torch.Tensor, gain: torch.Tensor, thresholds: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """inverse(soft_threshold_gain(y, ...)), fused where the plan allows it
+    (rows transformed in one workgroup), else the two steps."""
+    if plan.masked_inverse_supported:
+        return MaskedInverseFn.apply(y, gain, thresholds, plan)
+    return qtam_inverse(soft_threshold_gain(y, gain, thresholds, plan), plan)
+
+
 class GainThresholdDenoiser(torch.nn.Module):
     """Forward transform, a learnable gain per row times a soft-threshold mask
     on the envelope magnitudes, and the inverse transform:
@@ -104,5 +135,4 @@ class GainThresholdDenoiser(torch.nn.Module):
         self.register_buffer("thresholds", thresholds.to(rdt))
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
-        Y = self.qtam(x)
-        return self.qtam.inverse(soft_threshold_gain(Y, self.gain, self.thresholds, self.qtam.plan))
+        return masked_inverse(self.qtam(x), self.gain, self.thresholds, self.qtam.plan)

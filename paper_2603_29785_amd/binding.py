@@ -98,7 +98,8 @@ EXPORTED = [
     "qtam_forward_metric", "qtam_select_planes", "qtam_timing_enable", "qtam_timing_collect", "qtam_status_string",
     "qtam_dense", "qtam_dense_workspace_size", "qtam_tile_inverse", "qtam_last_error", "qtam_version",
     "qtam_forward_sweep", "qtam_forward_noalloc", "qtam_mask_forward", "qtam_mask_backward",
-    "qtam_mask_workspace_size",
+    "qtam_mask_workspace_size", "qtam_inverse_masked", "qtam_inverse_masked_adjoint",
+    "qtam_masked_adjoint_workspace_size",
 ]
 
 
@@ -129,6 +130,12 @@ def _load():
     L.qtam_mask_backward.restype = ctypes.c_int
     L.qtam_mask_workspace_size.argtypes = [vp, i64]
     L.qtam_mask_workspace_size.restype = sz
+    L.qtam_inverse_masked.argtypes = [vp, vp, vp, vp, vp, i64, vp, sz, vp]
+    L.qtam_inverse_masked.restype = ctypes.c_int
+    L.qtam_inverse_masked_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp, sz, vp]
+    L.qtam_inverse_masked_adjoint.restype = ctypes.c_int
+    L.qtam_masked_adjoint_workspace_size.argtypes = [vp, i64]
+    L.qtam_masked_adjoint_workspace_size.restype = sz
     L.qtam_forward_noalloc.argtypes = [vp, vp, vp, i64, vp]
     L.qtam_forward_noalloc.restype = ctypes.c_int
     L.qtam_tile_inverse.argtypes = [vp, vp, ctypes.c_int32, vp, i64, vp, sz, vp]
@@ -471,6 +478,72 @@ class Plan:
                                       ctypes.c_void_p(gy.data_ptr()), ctypes.c_void_p(dgain.data_ptr()),
                                       int(batch), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(wsb),
                                       ctypes.c_void_p(stream.cuda_stream)), "qtam_mask_backward")
+        return gy, dgain
+
+    @property
+    def masked_inverse_supported(self) -> bool:
+        """Whether inverse_masked / inverse_masked_adjoint run on this plan
+        (rows transformed in one workgroup); asks the library with an empty
+        batch."""
+        ok = getattr(self, "_masked_ok", None)
+        if ok is None:
+            st = lib.qtam_inverse_masked(self._h, None, None, None, None, 0, None, 0, None)
+            if st not in (QTAM_OK, QTAM_ERR_UNSUPPORTED):
+                _check(st, "qtam_inverse_masked")
+            ok = self._masked_ok = st == QTAM_OK
+        return ok
+
+    def inverse_masked(self, y, gain, thresholds, out=None, ws=None, stream=None):
+        """inverse(mask_forward(y, gain, thresholds)) in one pass over y: the
+        mask is applied as the inverse rows kernel loads the envelopes
+        (qtam_inverse_masked)."""
+        torch = self._torch()
+        y = self._check_rows(y)
+        gain = self._check_row_params(gain, "gain", y.device)
+        thresholds = self._check_row_params(thresholds, "thresholds", y.device)
+        lead = y.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        x = self._out(out, tuple(lead) + (self.N,), self._real_dtype(), y.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(y.device)
+        ws = self._workspace(batch, y.device, ws)
+        _check(lib.qtam_inverse_masked(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(gain.data_ptr()),
+                                       ctypes.c_void_p(thresholds.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                       int(batch), ctypes.c_void_p(ws.data_ptr()),
+                                       ctypes.c_size_t(ws.numel() * ws.element_size()),
+                                       ctypes.c_void_p(stream.cuda_stream)), "qtam_inverse_masked")
+        return x
+
+    def inverse_masked_adjoint(self, gx, y, gain, thresholds, ws=None, stream=None):
+        """(dL/dy, dL/dgain) of inverse_masked given gx = dL/dx
+        (qtam_inverse_masked_adjoint)."""
+        torch = self._torch()
+        gx = self._check_signal(gx)
+        y = self._check_rows(y)
+        if tuple(gx.shape[:-1]) != tuple(y.shape[:-2]) or gx.device != y.device:
+            raise ValueError("gx %s does not match y %s" % (tuple(gx.shape), tuple(y.shape)))
+        gain = self._check_row_params(gain, "gain", y.device)
+        thresholds = self._check_row_params(thresholds, "thresholds", y.device)
+        lead = y.shape[:-2]
+        batch = int(np.prod(lead)) if len(lead) else 1
+        gy = torch.empty_like(y)
+        dgain = torch.empty(self.R, dtype=self._real_dtype(), device=y.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(y.device)
+        if ws is not None:
+            ws = expect_workspace(ws, y.device)
+        else:
+            need = max(int(lib.qtam_masked_adjoint_workspace_size(self._h, int(batch))), 1)
+            if self._ws is None or self._ws.numel() < need or self._ws.device != y.device:
+                self._ws = torch.empty(need, dtype=torch.uint8, device=y.device)
+            ws = self._ws
+        _check(lib.qtam_inverse_masked_adjoint(self._h, ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                               ctypes.c_void_p(gain.data_ptr()),
+                                               ctypes.c_void_p(thresholds.data_ptr()),
+                                               ctypes.c_void_p(gy.data_ptr()), ctypes.c_void_p(dgain.data_ptr()),
+                                               int(batch), ctypes.c_void_p(ws.data_ptr()),
+                                               ctypes.c_size_t(ws.numel() * ws.element_size()),
+                                               ctypes.c_void_p(stream.cuda_stream)), "qtam_inverse_masked_adjoint")
         return gy, dgain
 
     def forward_metric(self, x, out=None, metric=None, ws=None, stream=None):

@@ -588,11 +588,25 @@ bool launch_spec_rows_twist(int log2l, const void* in, void* out, int64_t n2, in
   }
 }
 
+// The denoiser's mask fused into the row kernels of a masked inverse (gain,
+// lam) and of its adjoint (y: the unmasked envelopes; part: one partial sum
+// of the gain gradient per row of the chunk).
+struct MaskArgs {
+  const void* y;
+  const void* gain;
+  const void* lam;
+  void* part;
+};
+
 template <typename T>
 bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* out, const RowMeta* rows,
                  const void* roww, const void* tab, int R, int64_t total_rows, int64_t half, int64_t sum_len,
-                 const void* tw, hipStream_t st, void* stats = nullptr) {
+                 const void* tw, hipStream_t st, void* stats = nullptr, const MaskArgs* mk = nullptr) {
   using C = typename Complex<T>::type;
+  const C* my = mk ? static_cast<const C*>(mk->y) : nullptr;
+  const T* mg = mk ? static_cast<const T*>(mk->gain) : nullptr;
+  const T* ml = mk ? static_cast<const T*>(mk->lam) : nullptr;
+  T* mp = mk ? static_cast<T*>(mk->part) : nullptr;
   switch (log2l) {
 #define X(LG)                                                                                          \
   case LG:                                                                                             \
@@ -600,20 +614,22 @@ bool launch_rows(bool forward, bool analytic, int log2l, const void* in, void* o
       using Geo = RowGeom<T, (1 << LG)>;                                                               \
       const int blocks = static_cast<int>((total_rows + Geo::G - 1) / Geo::G);                         \
       if (forward) {                                                                                   \
-        auto kern = stats ? (analytic ? k_fwd_rows<T, (1 << LG), true, true>                          \
-                                      : k_fwd_rows<T, (1 << LG), false, true>)                         \
-                          : (analytic ? k_fwd_rows<T, (1 << LG), true, false>                          \
-                                      : k_fwd_rows<T, (1 << LG), false, false>);                       \
+        auto kern = mk ? k_fwd_rows<T, (1 << LG), false, false, true>                                  \
+                       : stats ? (analytic ? k_fwd_rows<T, (1 << LG), true, true>                      \
+                                           : k_fwd_rows<T, (1 << LG), false, true>)                    \
+                               : (analytic ? k_fwd_rows<T, (1 << LG), true, false>                     \
+                                           : k_fwd_rows<T, (1 << LG), false, false>);                  \
         hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(Geo::NT), 0, st, static_cast<const C*>(in), \
                            static_cast<C*>(out), rows, static_cast<const C*>(roww),                    \
                            static_cast<const T*>(tab), R, int(total_rows), int(half), int(sum_len),    \
                            (total_rows / R) * half, static_cast<const C*>(tw), blocks,                 \
-                           static_cast<C*>(stats));                                                    \
+                           static_cast<C*>(stats), my, mg, ml, mp);                                    \
       } else {                                                                                         \
-        hipLaunchKernelGGL((k_inv_rows<T, (1 << LG)>), dim3(unsigned(blocks)), dim3(Geo::NT), 0, st,   \
+        auto kern = mk ? k_inv_rows<T, (1 << LG), true> : k_inv_rows<T, (1 << LG), false>;            \
+        hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(Geo::NT), 0, st,                         \
                            static_cast<const C*>(in), static_cast<C*>(out), rows,                      \
                            static_cast<const T*>(tab), R, int(total_rows), int(sum_len),               \
-                           int(total_rows / R), static_cast<const C*>(tw));                           \
+                           int(total_rows / R), static_cast<const C*>(tw), mg, ml);                   \
       }                                                                                                \
       return true;                                                                                     \
     }                                                                                                  \
@@ -896,7 +912,7 @@ bool chirp_rows_long(qtam_plan_s* pl, bool forward, int table, const void* in, v
 // with T_AINV). Reads ws + lay.spec, writes y (and ws + lay.rows for long rows).
 template <typename T>
 bool analysis_rows(qtam_plan_s* pl, int table, void* y, int64_t segs, char* ws, const WsLayout& lay,
-                   hipStream_t st, void* stats) {
+                   hipStream_t st, void* stats, const MaskArgs* mk = nullptr) {
   const HostPlan& hp = pl->hp;
   const int64_t half = hp.half;
   void* spec = ws + lay.spec;
@@ -944,19 +960,20 @@ bool analysis_rows(qtam_plan_s* pl, int table, void* y, int64_t segs, char* ws, 
   Timed tm(pl, K_FWD_ROWS, st);
   return launch_rows<T>(true, table == T_FWD && pl->analytic_fwd, ilog2(hp.n_out), spec, y, pl->d_rows,
                         pl->d_roww, pl->d_tab[table], hp.rows, segs * hp.rows, half, hp.sum_len,
-                        pl->d_tw_out, st, stats);
+                        pl->d_tw_out, st, stats, mk);
 }
 
 template <typename T>
 bool run_analysis(qtam_plan_s* pl, int table, const void* x, void* y, int64_t segs, char* ws,
-                  const WsLayout& lay, hipStream_t st, void* stats) {
-  return analysis_spectrum<T>(pl, x, segs, ws, lay, st) && analysis_rows<T>(pl, table, y, segs, ws, lay, st, stats);
+                  const WsLayout& lay, hipStream_t st, void* stats, const MaskArgs* mk = nullptr) {
+  return analysis_spectrum<T>(pl, x, segs, ws, lay, st) &&
+         analysis_rows<T>(pl, table, y, segs, ws, lay, st, stats, mk);
 }
 
 // synthesis: rows -> real signal (inverse with T_DUAL, forward adjoint with T_AFWD)
 template <typename T>
 bool inverse_rows(qtam_plan_s* pl, int table, const void* y, int64_t segs, char* ws, const WsLayout& lay,
-                  hipStream_t st) {
+                  hipStream_t st, const MaskArgs* mk = nullptr) {
   using C = typename Complex<T>::type;
   const HostPlan& hp = pl->hp;
   const int64_t half = hp.half;
@@ -985,7 +1002,7 @@ bool inverse_rows(qtam_plan_s* pl, int table, const void* y, int64_t segs, char*
   } else {
     Timed tm(pl, K_INV_ROWS, st);
     ok = launch_rows<T>(false, false, ilog2(hp.n_out), y, pack, pl->d_rows, nullptr, pl->d_tab[table],
-                        hp.rows, segs * hp.rows, half, hp.sum_len, pl->d_tw_out, st);
+                        hp.rows, segs * hp.rows, half, hp.sum_len, pl->d_tw_out, st, nullptr, mk);
   }
   return ok;
 }
@@ -996,10 +1013,10 @@ bool synthesize(qtam_plan_s* pl, const void* pack, int64_t slen, const int* star
 
 template <typename T>
 bool run_synthesis(qtam_plan_s* pl, int table, const void* y, void* x, int64_t segs, char* ws,
-                   const WsLayout& lay, hipStream_t st) {
+                   const WsLayout& lay, hipStream_t st, const MaskArgs* mk = nullptr) {
   const HostPlan& hp = pl->hp;
   void* pack = ws + lay.pack;
-  bool ok = inverse_rows<T>(pl, table, y, segs, ws, lay, st);
+  bool ok = inverse_rows<T>(pl, table, y, segs, ws, lay, st, mk);
   if (!ok) return false;
   return synthesize<T>(pl, pack, hp.sum_len, pl->d_ola_start, pl->d_ola_rows, x, segs, ws, lay, st);
 }
@@ -1164,19 +1181,36 @@ bool launch_tile_rows(qtam_plan_s* pl, const void* y, void* sx, int row, int64_t
 
 enum Op { OP_FORWARD, OP_INVERSE, OP_FWD_ADJ, OP_INV_ADJ };
 
+// Bytes at the start of a masked adjoint's workspace for the gain
+// gradient's partial sums (one real per segment and row), 256-aligned.
+size_t mask_part_bytes(const qtam_plan_s* pl, int64_t batch) {
+  const size_t b = size_t(batch) * size_t(pl->hp.rows) * (pl->hp.precision == QTAM_FP64 ? 8 : 4);
+  return (b + 255) & ~size_t(255);
+}
+
+// mk: the denoiser's mask fused into a masked inverse (OP_INVERSE: gain,
+// lam) or its adjoint (OP_INV_ADJ: also y; the partial sums take the start
+// of ws and the gain gradient goes to dgain). Only rows transformed in one
+// workgroup (power-of-two N_out up to 32768 FP32 / 8192 FP64) take it.
 qtam_status run_op(qtam_plan_t pl, Op op, const void* in, void* out, int64_t batch, void* ws, size_t ws_bytes,
-                   qtam_stream_t stream, void* stats = nullptr) {
+                   qtam_stream_t stream, void* stats = nullptr, const MaskArgs* mk = nullptr,
+                   void* dgain = nullptr) {
   if (!pl || batch < 0) return QTAM_ERR_INVALID_ARG;
   if (batch == 0) return QTAM_OK;
   if (!in || !out || !ws) return QTAM_ERR_INVALID_ARG;
   if (!pl->gpu_supported) return pl->unsupported_reason;
   if (!pl->device) return QTAM_ERR_INVALID_ARG;
-  const int64_t chunk = std::min<int64_t>(chunk_for(pl, batch, ws_bytes), 65535);
-  if (chunk < 1) return QTAM_ERR_WORKSPACE;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (mk && (pl->big_rows || pl->bluestein)) return QTAM_ERR_UNSUPPORTED;
   const HostPlan& hp = pl->hp;
   const bool f64 = hp.precision == QTAM_FP64;
   const size_t rb = f64 ? 8 : 4;
+  const size_t part_bytes = (mk && op == OP_INV_ADJ) ? mask_part_bytes(pl, batch) : 0;
+  if (part_bytes && ws_bytes <= part_bytes) return QTAM_ERR_WORKSPACE;
+  char* part = static_cast<char*>(ws);
+  char* tws = static_cast<char*>(ws) + part_bytes;
+  const int64_t chunk = std::min<int64_t>(chunk_for(pl, batch, ws_bytes - part_bytes), 65535);
+  if (chunk < 1) return QTAM_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t x_seg = size_t(hp.n) * rb;
   const size_t y_seg = size_t(hp.rows) * size_t(hp.n_out) * 2 * rb;
   const bool analysis = (op == OP_FORWARD || op == OP_INV_ADJ);
@@ -1189,13 +1223,34 @@ qtam_status run_op(qtam_plan_t pl, Op op, const void* in, void* out, int64_t bat
     char* dst = static_cast<char*>(out) + size_t(b0) * (analysis ? y_seg : x_seg);
     bool ok;
     void* chunk_stats = stats ? static_cast<char*>(stats) + size_t(b0) * size_t(hp.rows) * 2 * rb : nullptr;
+    MaskArgs ck{};
+    const MaskArgs* cm = nullptr;
+    if (mk) {
+      ck = *mk;
+      if (op == OP_INV_ADJ) {
+        ck.y = static_cast<const char*>(mk->y) + size_t(b0) * y_seg;
+        ck.part = part + size_t(b0) * size_t(hp.rows) * rb;
+      }
+      cm = &ck;
+    }
     if (analysis)
-      ok = f64 ? run_analysis<double>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st, chunk_stats)
-               : run_analysis<float>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st, chunk_stats);
+      ok = f64 ? run_analysis<double>(pl, table, src, dst, segs, tws, lay, st, chunk_stats, cm)
+               : run_analysis<float>(pl, table, src, dst, segs, tws, lay, st, chunk_stats, cm);
     else
-      ok = f64 ? run_synthesis<double>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st)
-               : run_synthesis<float>(pl, table, src, dst, segs, static_cast<char*>(ws), lay, st);
+      ok = f64 ? run_synthesis<double>(pl, table, src, dst, segs, tws, lay, st, cm)
+               : run_synthesis<float>(pl, table, src, dst, segs, tws, lay, st, cm);
     if (!ok) return QTAM_ERR_UNSUPPORTED;
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
+  }
+  if (part_bytes) {
+    // the gain gradient: the rows' partial sums added over the segments
+    Timed tm(pl, K_MASK_BWD, st);
+    if (f64)
+      hipLaunchKernelGGL((k_gain_sum<double>), dim3(unsigned(hp.rows)), dim3(64), 0, st,
+                         reinterpret_cast<const double*>(part), static_cast<double*>(dgain), hp.rows, batch);
+    else
+      hipLaunchKernelGGL((k_gain_sum<float>), dim3(unsigned(hp.rows)), dim3(64), 0, st,
+                         reinterpret_cast<const float*>(part), static_cast<float*>(dgain), hp.rows, batch);
     if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
   }
   return QTAM_OK;
@@ -1729,6 +1784,46 @@ qtam_status qtam_forward_adjoint(qtam_plan_t pl, const void* gy, void* gx, int64
 qtam_status qtam_inverse_adjoint(qtam_plan_t pl, const void* gx, void* gy, int64_t batch, void* ws,
                                  size_t ws_bytes, qtam_stream_t stream) {
   return run_op(pl, OP_INV_ADJ, gx, gy, batch, ws, ws_bytes, stream);
+}
+
+qtam_status qtam_inverse_masked(qtam_plan_t pl, const void* y, const void* gain, const void* lambda, void* x,
+                                int64_t batch, void* ws, size_t ws_bytes, qtam_stream_t stream) {
+  if (!pl || batch < 0) return QTAM_ERR_INVALID_ARG;
+  if (!pl->gpu_supported) return pl->unsupported_reason;
+  if (pl->big_rows || pl->bluestein) return QTAM_ERR_UNSUPPORTED;   // also for batch = 0: a query
+  if (batch == 0) return QTAM_OK;
+  if (!gain || !lambda) return QTAM_ERR_INVALID_ARG;
+  const MaskArgs mk{nullptr, gain, lambda, nullptr};
+  return run_op(pl, OP_INVERSE, y, x, batch, ws, ws_bytes, stream, nullptr, &mk);
+}
+
+size_t qtam_masked_adjoint_workspace_size(qtam_plan_t pl, int64_t batch) {
+  if (!pl || batch < 1) return 0;
+  return mask_part_bytes(pl, batch) + layout_for(pl, batch).total;
+}
+
+qtam_status qtam_inverse_masked_adjoint(qtam_plan_t pl, const void* gx, const void* y, const void* gain,
+                                        const void* lambda, void* gy, void* dgain, int64_t batch, void* ws,
+                                        size_t ws_bytes, qtam_stream_t stream) {
+  if (!pl || batch < 0 || !gain || !lambda || !dgain) return QTAM_ERR_INVALID_ARG;
+  if (batch > 0 && !y) return QTAM_ERR_INVALID_ARG;
+  if (!pl->gpu_supported) return pl->unsupported_reason;
+  if (pl->big_rows || pl->bluestein) return QTAM_ERR_UNSUPPORTED;
+  if (!pl->device) return QTAM_ERR_INVALID_ARG;
+  if (batch == 0) {   // dgain = 0
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    if (pl->hp.precision == QTAM_FP64)
+      hipLaunchKernelGGL((k_gain_sum<double>), dim3(unsigned(pl->hp.rows)), dim3(64), 0, st, nullptr,
+                         static_cast<double*>(dgain), pl->hp.rows, int64_t(0));
+    else
+      hipLaunchKernelGGL((k_gain_sum<float>), dim3(unsigned(pl->hp.rows)), dim3(64), 0, st, nullptr,
+                         static_cast<float*>(dgain), pl->hp.rows, int64_t(0));
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return hip_failed(e, "kernel launch");
+    return QTAM_OK;
+  }
+  const MaskArgs mk{y, gain, lambda, nullptr};
+  return run_op(pl, OP_INV_ADJ, gx, gy, batch, ws, ws_bytes, stream, nullptr, &mk, dgain);
 }
 
 qtam_status qtam_timing_enable(qtam_plan_t pl, int32_t on) {

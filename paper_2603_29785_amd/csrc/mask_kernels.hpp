@@ -7,8 +7,8 @@
 //             dL/dy = g_k * (m G + [m > 0 and lambda_k > 0] lambda_k p / |y|^3 * y),
 //             dL/dg_k = sum over b and m of m p.
 // |y| is floored at the smallest normal number (no 0/0 where y = 0), and
-// lambda p / |y|^3 is formed as (lambda/|y|)(p/|y|)/|y|, which stays finite
-// wherever m > 0 (there |y| > lambda and |p| <= |y| |G|).
+// lambda p / |y|^3 is formed as (lambda/|y|) (p (1/|y|)) (1/|y|), which stays
+// finite wherever m > 0 (there |y| > lambda and |p| <= |y| |G|).
 #pragma once
 
 #include "device_common.hpp"
@@ -22,6 +22,23 @@ struct MaskMath {
   static __device__ __forceinline__ T absc(C v) { return fmax(sqrt(fmadd(v.x, v.x, v.y * v.y)), tiny()); }
   // mask value max(0, 1 - lambda / r)
   static __device__ __forceinline__ T mask(T lam, T r) { return fmax(T(0), T(1) - lam / r); }
+  // g * mask * v
+  static __device__ __forceinline__ C apply(C v, T g, T lam) {
+    const T s = mask(lam, absc(v)) * g;
+    return C{v.x * s, v.y * s};
+  }
+  // dL/dv of apply at v for the incoming gradient G; adds m p to acc. Two
+  // divisions: q = lambda / r (the mask's own quotient) and 1 / r.
+  static __device__ __forceinline__ C grad(C v, C G, T g, T lam, T& acc) {
+    const T r = absc(v);
+    const T q = lam / r;
+    const T mk = fmax(T(0), T(1) - q);
+    const T p = fmadd(v.x, G.x, v.y * G.y);
+    const T ir = T(1) / r;
+    const T c = (mk > T(0) && lam > T(0)) ? q * (p * ir) * ir : T(0);
+    acc = fmadd(mk, p, acc);
+    return C{g * fmadd(c, v.x, mk * G.x), g * fmadd(c, v.y, mk * G.y)};
+  }
 };
 
 // Elementwise forward over [segs, R, L] (L = N_out), grid (ceil(L / 256), segs * R).
@@ -36,9 +53,7 @@ __global__ __launch_bounds__(256) void k_mask_fwd(const typename Complex<T>::typ
   const int64_t gr = blockIdx.y;
   const int k = static_cast<int>(gr % R);
   const int64_t i = gr * L + m;
-  const C v = y[i];
-  const T s = M::mask(lam[k], M::absc(v)) * gain[k];
-  out[i] = C{v.x * s, v.y * s};
+  out[i] = M::apply(y[i], gain[k], lam[k]);
 }
 
 // Backward, one workgroup per row (segment, k): dL/dy elementwise, and the
@@ -60,15 +75,7 @@ __global__ __launch_bounds__(256) void k_mask_bwd(const typename Complex<T>::typ
   const C* gor = gout + gr * L;
   C* gyr = gy + gr * L;
   T acc = 0;
-  for (int m = threadIdx.x; m < L; m += 256) {
-    const C v = yr[m], G = gor[m];
-    const T r = M::absc(v);
-    const T mk = M::mask(lk, r);
-    const T p = fmadd(v.x, G.x, v.y * G.y);
-    const T c = (mk > T(0) && lk > T(0)) ? (lk / r) * (p / r) / r : T(0);
-    gyr[m] = C{gk * fmadd(c, v.x, mk * G.x), gk * fmadd(c, v.y, mk * G.y)};
-    acc = fmadd(mk, p, acc);
-  }
+  for (int m = threadIdx.x; m < L; m += 256) gyr[m] = M::grad(yr[m], gor[m], gk, lk, acc);
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {

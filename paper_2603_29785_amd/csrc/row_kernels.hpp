@@ -7,6 +7,7 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "mask_kernels.hpp"
 
 namespace qtam {
 
@@ -134,17 +135,49 @@ __device__ __forceinline__ void row_stats(const typename Complex<T>::type (&v)[E
   }
 }
 
+// Sum of one value per thread over each row of the block, in a fixed order:
+// an xor butterfly over a row's lanes within a wave, then (rows spanning
+// several waves) the per-wave sums in wave order through `part` (LDS the
+// transform no longer reads, NT/64 elements). Every thread of the block must
+// call it.
+template <typename T, int TPR, int NT>
+__device__ __forceinline__ void row_sum(T s, int tl, bool ok, T* __restrict__ dst, T* __restrict__ part) {
+  constexpr int W = TPR < 64 ? TPR : 64;
+  constexpr int WPR = TPR > 64 ? TPR / 64 : 1;
+#pragma unroll
+  for (int o = 1; o < W; o <<= 1) s += __shfl_xor(s, o, W);
+  if constexpr (WPR == 1) {
+    if (ok && tl == 0) *dst = s;
+  } else {
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (ok && tl == 0) {
+      const T* pr = part + (threadIdx.x >> 6);
+      T r = pr[0];
+#pragma unroll
+      for (int w = 1; w < WPR; ++w) r += pr[w];
+      *dst = r;
+    }
+  }
+}
+
 // When a wave holds one row (TPR >= 64) and the row touches neither DC nor
 // Nyquist, buffer resources scoped to the row's kept support do the cropping:
 // slots outside it fall outside the resources and read 0, with no test.
 // Otherwise each slot is tested; ANALYTIC then computes the bisquare weight
 // scale_k (1 - (j/h_k)^2)^2 instead of reading the table.
-template <typename T, int L, bool ANALYTIC, bool STATS>
+// MBWD (the inverse adjoint of a masked inverse): the transform's output is
+// the gradient G with respect to the masked envelope Y' = g_k m Y; the kernel
+// reads Y (mY, same layout as the output) and stores dL/dY instead, and the
+// row's sum of m Re(conj(Y) G) goes to mpart[row] (the gain gradient's share).
+template <typename T, int L, bool ANALYTIC, bool STATS, bool MBWD = false>
 __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
     const typename Complex<T>::type* __restrict__ spec, typename Complex<T>::type* __restrict__ Y,
     const RowMeta* __restrict__ rows, const typename Complex<T>::type* __restrict__ roww,
     const T* __restrict__ tab, int R, int total, int half, int sum_len, int64_t spec_elems,
-    const typename Complex<T>::type* __restrict__ tw, int nblocks, typename Complex<T>::type* __restrict__ stats) {
+    const typename Complex<T>::type* __restrict__ tw, int nblocks, typename Complex<T>::type* __restrict__ stats,
+    const typename Complex<T>::type* __restrict__ mY, const T* __restrict__ mgain, const T* __restrict__ mlam,
+    T* __restrict__ mpart) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, +1, TW_MIXED>;
@@ -234,20 +267,36 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_fwd_rows(
   const int64_t nrow = total - r0 < Geo::G ? total - r0 : Geo::G;
   const rsrc_t ry = make_rsrc(Y + r0 * L, static_cast<uint32_t>(nrow * L * sizeof(C)));
   const uint32_t vb = static_cast<uint32_t>(g * L + tl) * sizeof(C);
+  if constexpr (MBWD) {
+    const rsrc_t rm = make_rsrc(mY + r0 * L, static_cast<uint32_t>(nrow * L * sizeof(C)));
+    const T gk = ok ? mgain[row] : T(0), lk = ok ? mlam[row] : T(0);
+    T acc = 0;
 #pragma unroll
-  for (int i = 0; i < Geo::E; ++i) bstore<C, kYStore>(ry, v[i], vb, F::out_off(i) * sizeof(C));
-  if constexpr (STATS) row_stats<T, Geo::E, Geo::TPR, Geo::NT>(v, tl, ok, stats + gr, lds);
+    for (int i = 0; i < Geo::E; ++i) {
+      const C yv = bload<C>(rm, vb, F::out_off(i) * sizeof(C));
+      v[i] = MaskMath<T>::grad(yv, v[i], gk, lk, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) bstore<C, kYStore>(ry, v[i], vb, F::out_off(i) * sizeof(C));
+    row_sum<T, Geo::TPR, Geo::NT>(acc, tl, ok, mpart + gr, reinterpret_cast<T*>(lds));
+  } else {
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) bstore<C, kYStore>(ry, v[i], vb, F::out_off(i) * sizeof(C));
+    if constexpr (STATS) row_stats<T, Geo::E, Geo::TPR, Geo::NT>(v, tl, ok, stats + gr, lds);
+  }
 }
 
 // Inverse rows: N_out-point FFT of each envelope row; the kept slots times the
 // table go to the packed per-segment buffer Sbuf[seg * sum_len + off + c - lo].
 // With one row per wave, resources scoped to the row's packed entries drop
 // the other slots' stores without a test.
-template <typename T, int L>
+// MASK (a masked inverse): each loaded value y becomes g_k max(0, 1 -
+// lambda_k / |y|) y (the mask of the denoiser) before the transform.
+template <typename T, int L, bool MASK = false>
 __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
     const typename Complex<T>::type* __restrict__ Y, typename Complex<T>::type* __restrict__ Sbuf,
     const RowMeta* __restrict__ rows, const T* __restrict__ tab, int R, int total, int sum_len, int segs,
-    const typename Complex<T>::type* __restrict__ tw) {
+    const typename Complex<T>::type* __restrict__ tw, const T* __restrict__ mgain, const T* __restrict__ mlam) {
   using C = typename Complex<T>::type;
   using Geo = RowGeom<T, L>;
   using F = BlockFft<T, L, Geo::E, -1, TW_MIXED>;
@@ -261,6 +310,14 @@ __global__ __launch_bounds__((RowGeom<T, L>::NT)) void k_inv_rows(
   C v[Geo::E];
 #pragma unroll
   for (int i = 0; i < Geo::E; ++i) v[i] = bload<C, kYLoad>(ry, vb, F::in_off(i) * sizeof(C));
+  if constexpr (MASK) {
+    int gm = static_cast<int>(r0) + g;
+    if constexpr (kWaveRow) gm = __builtin_amdgcn_readfirstlane(gm);
+    const int km = gm < total ? gm % R : 0;
+    const T gk = mgain[km], lk = mlam[km];
+#pragma unroll
+    for (int i = 0; i < Geo::E; ++i) v[i] = MaskMath<T>::apply(v[i], gk, lk);
+  }
   if constexpr (kWaveRow) {
     // the row's weights are requested before the transform, so their latency
     // hides behind it; rows past the end get empty resources

@@ -367,3 +367,31 @@ def test_mask_entry_points_validate_without_device(precision, b):
     assert L.qtam_mask_backward(gp._h, *args, -1, dummy, ws, None) == inv
     assert L.qtam_mask_backward(None, *args, 2, dummy, ws, None) == inv
     assert L.qtam_mask_backward(gp._h, dummy, None, dummy, dummy, dummy, dummy, 0, None, 0, None) == inv
+
+
+def test_masked_inverse_support_and_validation_without_device():
+    """The fused mask + inverse calls: supported where rows take one
+    workgroup (an empty batch asks), QTAM_ERR_UNSUPPORTED on two-pass rows
+    (FP64 rows of 16384 points); workspace = the partial sums (256-aligned)
+    + the transform's; argument checks before any device work."""
+    L = binding.lib
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: the calls fail validation first
+    gp = host_plan(sample_rate=4096.0, n_samples=32768, q=8.0, f_min=20.0, f_max=2000.0, n_rows=128)
+    assert gp.masked_inverse_supported
+    assert L.qtam_masked_adjoint_workspace_size(gp._h, 3) == (3 * 128 * 4 + 255) // 256 * 256 + gp.workspace_bytes(3)
+    assert L.qtam_masked_adjoint_workspace_size(gp._h, 0) == 0
+    ws = L.qtam_masked_adjoint_workspace_size(gp._h, 2)
+    inv = binding.QTAM_ERR_INVALID_ARG
+    assert L.qtam_inverse_masked(gp._h, dummy, dummy, dummy, dummy, 2, dummy, ws, None) == inv   # no device tables
+    assert L.qtam_inverse_masked(gp._h, dummy, None, dummy, dummy, 2, dummy, ws, None) == inv
+    assert L.qtam_inverse_masked(None, dummy, dummy, dummy, dummy, 2, dummy, ws, None) == inv
+    args = (dummy, dummy, dummy, dummy, dummy, dummy)
+    assert L.qtam_inverse_masked_adjoint(gp._h, *args, 2, dummy, ws, None) == inv
+    assert L.qtam_inverse_masked_adjoint(gp._h, *args, -1, dummy, ws, None) == inv
+    assert L.qtam_inverse_masked_adjoint(gp._h, dummy, dummy, dummy, dummy, dummy, None, 2, dummy, ws, None) == inv
+    long_rows = host_plan(sample_rate=4096.0, n_samples=24576, q=8.0, f_min=10.0, f_max=2048.0, n_rows=62,
+                          precision="fp64", n_out=16384)
+    assert not long_rows.masked_inverse_supported
+    uns = binding.QTAM_ERR_UNSUPPORTED
+    assert L.qtam_inverse_masked(long_rows._h, None, None, None, None, 0, None, 0, None) == uns
+    assert L.qtam_inverse_masked_adjoint(long_rows._h, *args, 1, dummy, ws, None) == uns
