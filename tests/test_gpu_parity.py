@@ -505,6 +505,14 @@ BUDGET_PLANS = [
      o.WIN_KAISER, 5.0, 32768),
     ("256 Hz Kaiser from 10 Hz", 256.0, 262144, 5.8947755089717955, 10.0, 128.0, 60, "kaiser",
      o.WIN_KAISER, 5.0, 32768),
+    # random plans found nearest the FP32 bar (about 5e-6) in a sweep: bands
+    # from 15-22 Hz at 256 Hz, Pbar / P_X about 1000-1500, the budget's edge
+    ("256 Hz Kaiser Q 2 from 21 Hz, odd N_out", 256.0, 81920, 2.009339606116827, 21.419685991304572, 128.0, 12,
+     "kaiser", o.WIN_KAISER, 5.0, 12348),
+    ("256 Hz Kaiser Q 6.6 from 21.5 Hz", 256.0, 65536, 6.64808106438729, 21.528150558862084, 128.0, 35, "kaiser",
+     o.WIN_KAISER, 5.0, 0),
+    ("256 Hz Kaiser Q 5 from 15 Hz", 256.0, 98304, 5.046765315259778, 15.241534846108705, 128.0, 19, "kaiser",
+     o.WIN_KAISER, 5.0, 0),
 ]
 
 
@@ -512,7 +520,7 @@ BUDGET_PLANS = [
 def test_fp32_coefficient_error_budget(torch_dev, spec):
     """FP32 coefficients on coloured noise with injections: within the bar and
     within twice the budget above, on plans whose coloured noise below the
-    band raises Pbar / P_X from about 4 to about 700."""
+    band raises Pbar / P_X from about 4 to about 1500."""
     torch = torch_dev
     import paper_2603_29785_amd as qt
     what, fs, n, q, fmin, fmax, rows, wname, wid, wparam, n_out = spec
