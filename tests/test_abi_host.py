@@ -395,3 +395,22 @@ def test_masked_inverse_support_and_validation_without_device():
     uns = binding.QTAM_ERR_UNSUPPORTED
     assert L.qtam_inverse_masked(long_rows._h, None, None, None, None, 0, None, 0, None) == uns
     assert L.qtam_inverse_masked_adjoint(long_rows._h, *args, 1, dummy, ws, None) == uns
+
+
+def test_header_compiles_as_c99_and_cxx17(tmp_path):
+    """include/qtam.h is a plain C header: it compiles as strict C99 and as
+    C++17, with every entry point referenced."""
+    import shutil
+    import subprocess
+    hdr = open(os.path.join(ROOT, "include", "qtam.h")).read()
+    names = sorted(set(re.findall(r"\b(qtam_[a-z0-9_]+)\s*\(", hdr)))
+    assert "qtam_inverse_masked_adjoint" in names and "qtam_forward_noalloc" in names
+    src = tmp_path / "use.c"
+    src.write_text('#include "qtam.h"\ntypedef void (*fn)(void);\nfn table[] = {' +
+                   ", ".join("(fn)" + n for n in names) + "};\nint main(void) { return table[0] == 0; }\n")
+    for cc, std, lang in (("gcc", "-std=c99", "c"), ("g++", "-std=c++17", "c++")):
+        if shutil.which(cc) is None:
+            pytest.skip(cc + " not available")
+        r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-x", lang,
+                            "-I" + os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
