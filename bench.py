@@ -362,8 +362,11 @@ def main():
         del ys, xr, ws
         torch.cuda.empty_cache()
         out["serving"] = serving_leg(200.0, 10.0, sweep_rates=(5000.0,), sweep_duration=5.0)
+    served = out["serving"].pop("served_sample") if "serving" in out else []
     if not args.no_cpu:
         out.update(cpu_leg(args, plans, x_host, x, B, W))
+        if "serving" in out:
+            out["serving"]["serving"]["checked"] = oracle_check_served(served)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -384,11 +387,11 @@ OTHER_WORKLOADS = {
 
 def other_workload(args):
     """One of the other workloads: steps timed with HIP events, samples/s,
-    latency, and the error against the FP64 oracle on one segment."""
+    latency; the CPU leg adds the oracle on one segment (its time and the
+    GPU's error against it)."""
     import torch
     import paper_2603_29785_amd as qt
     import synthetic
-    from oracle import oracle as o
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -450,17 +453,8 @@ def other_workload(args):
                       "precision": args.precision},
            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                           "what": "one step, HIP events"}}
-    # error of segment 0 against the oracle (same input bits)
-    op = o.OraclePlan(fs=fs, n=n, q=W["q"], f_min=W["f_min"], f_max=W["f_max"], rows=W["rows"])
-    x0 = x[0].double().cpu().numpy()
-    Yo = op.forward(x0)
-    Yg = plan.forward(x[0:1].contiguous())[0].cpu().numpy()
-    Yc = Yo.astype(np.complex128 if fp64 else np.complex64)   # the oracle's coefficients in device precision
-    xg = plan.inverse(torch.from_numpy(Yc[None]).to("cuda"))[0].cpu().numpy()
-    xo = op.inverse(Yc.astype(np.complex128))
-    out["recon_rel_err"] = {"coef": float(np.linalg.norm(Yg - Yo) / np.linalg.norm(Yo)),
-                            "recon": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
-                            "segments": 1, "vs": "FP64 CPU oracle", "precision": args.precision}
+    if not args.no_cpu:
+        out.update(cpu_leg_one_segment(args, plan, W, x, fp64))
     print(json.dumps(out), flush=True)
     return 0
 
@@ -501,6 +495,49 @@ def composite_leg(args, x, B, W, ms_main):
             "speed_vs_main_step": ms_main / ms, "best_plane_counts": counts,
             "what": "forward with row statistics + energy selection + inverse of one %d-row bank "
                     "(Q %s), samples counted once per plane" % (p.R, list(W["qs"]))}
+
+
+# ---------------------------------------------------------------------------
+# The CPU leg: the only part of the benchmark that runs the FP64 oracle. It
+# times the oracle on the host (cpu_baseline) and measures the GPU results'
+# error against it on the same input bits.
+# ---------------------------------------------------------------------------
+def cpu_leg_one_segment(args, plan, W, x_dev, fp64):
+    """The other workloads' CPU leg: the oracle's forward and inverse of
+    segment 0 on one host core, and the GPU's coefficients (same input bits)
+    and inverse (of the oracle's coefficients rounded to the device
+    precision) against it."""
+    import torch
+    from oracle import oracle as o
+    n = W["n"]
+    op = o.OraclePlan(fs=W["fs"], n=n, q=W["q"], f_min=W["f_min"], f_max=W["f_max"], rows=W["rows"])
+    x0 = x_dev[0].double().cpu().numpy()
+    t0 = time.perf_counter()
+    Yo = op.forward(x0)
+    Yc = Yo.astype(np.complex128 if fp64 else np.complex64)   # the oracle's coefficients in device precision
+    xo = op.inverse(Yc.astype(np.complex128))
+    t = time.perf_counter() - t0
+    Yg = plan.forward(x_dev[0:1].contiguous())[0].cpu().numpy()
+    xg = plan.inverse(torch.from_numpy(Yc[None]).to("cuda"))[0].cpu().numpy()
+    return {"recon_rel_err": {"coef": float(np.linalg.norm(Yg - Yo) / np.linalg.norm(Yo)),
+                              "recon": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
+                              "segments": 1, "vs": "FP64 CPU oracle", "precision": args.precision},
+            "cpu_baseline": {"value": n / t, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                             "sample": "segment 0: one FP64 forward + inverse, %.1f ms, single thread" % (1e3 * t),
+                             "host": cpu_model()}}
+
+
+def oracle_check_served(served):
+    """Served reconstructions (a sample spread over the serving stream)
+    against the oracle's reconstruction x_M of the same input bits."""
+    from oracle import oracle as o
+    errs = []
+    for k, x, result in served:
+        op = o.OraclePlan(fs=k.fs, n=k.n, q=k.q, f_min=k.f_min, f_max=k.f_max, rows=k.rows)
+        xm = op.project(x)
+        errs.append(float(np.linalg.norm(result - xm) / np.linalg.norm(xm)))
+    return {"requests": len(errs), "max_rel_err": max(errs) if errs else None,
+            "what": "served reconstruction vs the FP64 oracle's x_M, rel-L2, on requests spread over the stream"}
 
 
 def _oracle_worker(job):
@@ -603,11 +640,10 @@ def serving_leg(rate, duration, sweep_rates=(), sweep_duration=10.0, burst_n=400
     continuous-batching server (payloads in pinned host memory, as a client
     hands them over); then a saturation sweep, and a burst against the plain
     one-segment-per-launch form on the same requests. A sample of the served
-    results (check_n requests spread over the stream) is compared with the
-    FP64 oracle's reconstruction x_M on the same input bits."""
+    results (check_n requests spread over the stream) is kept, with its
+    inputs, for the CPU leg to compare with the oracle (oracle_check_served)."""
     import torch
     import synthetic
-    from oracle import oracle as ora
     from paper_2603_29785_amd.serving import BucketKey, GpuExecutor, Request, Server, plain_run
 
     torch.cuda.set_device(0)
@@ -661,18 +697,8 @@ def serving_leg(rate, duration, sweep_rates=(), sweep_duration=10.0, burst_n=400
     st["offered_samples_per_s"] = sum(a.n for a in arrivals) / duration
     print("serving at %g/s: %s" % (rate, st), file=sys.stderr, flush=True)
 
-    # served results against the FP64 oracle's reconstruction x_M of the same input bits
-    errs = []
-    for r, a in made:
-        if r.status != "done":
-            continue
-        k = r.key
-        op = ora.OraclePlan(fs=k.fs, n=k.n, q=k.q, f_min=k.f_min, f_max=k.f_max, rows=k.rows)
-        xm = op.project(r.data.numpy().astype(np.float64))
-        errs.append(float(np.linalg.norm(r.result - xm) / np.linalg.norm(xm)))
-    st["checked"] = {"requests": len(errs), "max_rel_err": max(errs) if errs else None,
-                     "what": "served reconstruction vs the FP64 oracle's x_M, rel-L2, on requests spread "
-                             "over the stream"}
+    # a sample of served results with their input bits, for the oracle check of the CPU leg
+    served = [(r.key, r.data.numpy().astype(np.float64), r.result) for r, a in made if r.status == "done"]
 
     sweep = []
     for sr in sweep_rates:
@@ -713,7 +739,7 @@ def serving_leg(rate, duration, sweep_rates=(), sweep_duration=10.0, burst_n=400
         "latency_ms": {"p50": st.get("p50_ms"), "p99": st.get("p99_ms"), "max": st.get("max_ms"),
                        "what": "arrival (payload in pinned host memory) to the reconstruction back in pinned "
                                "host memory: H2D, forward+inverse, D2H"},
-        "serving": st, "sweep": sweep,
+        "serving": st, "sweep": sweep, "served_sample": served,
         "burst": {"requests": len(burst), "seconds": t_srv, "serving_samples_per_s": samples / t_srv,
                   "plain_samples_per_s": samples / t_plain, "speedup": t_plain / t_srv,
                   "identical_results": same, "what": "burst at saturation: continuous batching vs one "
@@ -725,6 +751,9 @@ def serving_main(args):
     """The serving workload alone, as its own bench line."""
     sweep = [float(r) for r in args.sweep.split(",") if r]
     leg = serving_leg(args.rate, args.duration, sweep, min(args.duration, 10.0), 400, args.hbm_budget_gb)
+    served = leg.pop("served_sample")
+    if not args.no_cpu:
+        leg["serving"]["checked"] = oracle_check_served(served)
     b = leg["burst"]
     out = {
         "metric": "fwd+inv QTAM samples/s @1 GPU; p50/p99 latency; recon rel-err vs FP64",
