@@ -414,3 +414,21 @@ def test_header_compiles_as_c99_and_cxx17(tmp_path):
         r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", "-x", lang,
                             "-I" + os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
         assert r.returncode == 0, r.stderr
+
+
+def test_c_caller_without_python_or_gpu(tmp_path):
+    """tests/c_abi_host.c, a plain C99 caller linked against libqtam.so, runs
+    on a machine without a GPU: host-only plans, their tables (the frame is
+    the sum of the squared windows), workspace sizes and status codes."""
+    import shutil
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    libdir = os.path.dirname(binding.LIB_PATH)
+    exe = tmp_path / "c_abi_host"
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I" + os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "c_abi_host.c"),
+                        "-o", str(exe), "-L" + libdir, "-lqtam", "-Wl,-rpath," + libdir, "-lm"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.rstrip().endswith("PASSED"), r.stdout + r.stderr
