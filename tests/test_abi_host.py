@@ -432,3 +432,17 @@ def test_c_caller_without_python_or_gpu(tmp_path):
     assert r.returncode == 0, r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.rstrip().endswith("PASSED"), r.stdout + r.stderr
+
+
+def test_mask_binding_rejects_host_tensors():
+    """The mask and masked-inverse methods take device tensors only: host
+    tensors raise before any pointer reaches the library."""
+    import torch
+    gp = host_plan(sample_rate=4096.0, n_samples=32768, q=8.0, f_min=20.0, f_max=2000.0, n_rows=128)
+    y = torch.zeros((1, gp.R, gp.N_out), dtype=torch.complex64)
+    g = torch.ones(gp.R)
+    x = torch.zeros((1, gp.N))
+    for call in (lambda: gp.mask_forward(y, g, g), lambda: gp.mask_backward(y, g, g, y),
+                 lambda: gp.inverse_masked(y, g, g), lambda: gp.inverse_masked_adjoint(x, y, g, g)):
+        with pytest.raises(TypeError):
+            call()
