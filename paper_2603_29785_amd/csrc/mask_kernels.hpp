@@ -46,7 +46,6 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_mask_fwd(const typename Complex<T>::type* __restrict__ y,
                                                   const T* __restrict__ gain, const T* __restrict__ lam,
                                                   typename Complex<T>::type* __restrict__ out, int R, int L) {
-  using C = typename Complex<T>::type;
   using M = MaskMath<T>;
   const int m = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
   if (m >= L) return;
