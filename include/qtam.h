@@ -107,10 +107,12 @@ typedef struct {
   const double* plane_q;
   const int32_t* plane_window;
   const double* plane_window_param;
-  /* Regularised stop band (Sec. III; App. A): > 0 gives every window this
-   * value (before normalisation) on every bin of 0..N/2 where its shape is
-   * zero, so each row keeps the whole band (max L_k = N/2 + 1) and a single
-   * tile determines the signal (qtam_tile_inverse). 0: plain windows.      */
+  /* Regularised stop band (Sec. III; App. A): > 0 is a floor on every
+   * window (before normalisation): each bin of 0..N/2 where its shape is
+   * below this value (the stop band, the support's end points, a taper's
+   * tails) takes this value, so each row keeps the whole band (max L_k =
+   * N/2 + 1) and a single tile determines the signal (qtam_tile_inverse)
+   * with rounding amplified by at most about 1/window_eps. 0: plain windows. */
   double window_eps;
 } qtam_params;
 

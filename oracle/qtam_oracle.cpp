@@ -234,8 +234,11 @@ struct PlaneSpec {
 // Returns 0 on success, 1 on invalid parameters. Rows are plane after plane,
 // each plane over the same frequency grid.
 // eps > 0: every window takes the value eps on the bins of the one-sided
-// band where its shape is zero (Sec. III regularised stop band; App. A),
-// before the normalisation, so that it is non-zero on all bins 0..N/2.
+// band where its shape is below eps (Sec. III regularised stop band; App. A:
+// the stop band, the support's end points and the tails of a taper below
+// eps), before the normalisation, so that it is at least eps times its peak
+// on all bins 0..N/2 and a single tile is invertible with rounding amplified
+// by at most about 1/eps.
 int build_plan(Plan& pl, double fs, int64_t n, const std::vector<PlaneSpec>& planes, double fmin,
                double fmax, int32_t nrows, const double* freqs, int32_t cap_mode, int32_t max_window,
                int32_t norm_mode, int32_t n_out, double tau, double eps) {
@@ -323,12 +326,13 @@ int build_plan(Plan& pl, double fs, int64_t n, const std::vector<PlaneSpec>& pla
     r.w.assign(static_cast<size_t>(r.hi - r.lo + 1), 0.0);
     double energy = 0.0;
     for (int64_t c = r.lo; c <= r.hi; ++c) {
-      // the stop band is every bin where the shape vanishes, the support's
-      // own end points included (the bisquare is zero there)
+      // eps is a floor: every bin where the shape is below it (the stop band,
+      // the support's own end points where the bisquare is zero, the tails
+      // of a taper that fall below eps) takes the value eps
       const bool inside = c >= r.s - h && c <= r.s + h;
       const double x = static_cast<double>(c - r.s) / static_cast<double>(h);
       double v = inside ? window_shape(window, x, window_param) : 0.0;
-      if (eps > 0.0 && v == 0.0) v = eps;
+      if (eps > 0.0 && v < eps) v = eps;
       r.w[static_cast<size_t>(c - r.lo)] = v;
       energy += v * v;
     }

@@ -175,7 +175,7 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
     for (int64_t c = a; c <= b; ++c) {
       const bool inside = c >= s - h && c <= s + h;
       double w = inside ? shape(plane.window, static_cast<double>(c - s) / static_cast<double>(h), plane.param) : 0.0;
-      if (hp.eps > 0.0 && w == 0.0) w = hp.eps;   // the stop band, support end points included
+      if (hp.eps > 0.0 && w < hp.eps) w = hp.eps;   // floor: the stop band, end points, tails below eps
       hp.win.push_back(w);
       e2 += w * w;
     }

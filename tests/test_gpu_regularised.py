@@ -89,3 +89,28 @@ def test_single_tile_needs_regularised_windows(torch_dev):
     with pytest.raises(qt.QtamError) as e:
         gp.tile_inverse(y, 0)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_planck_taper_tails_single_tile(torch_dev, precision):
+    """A Planck-taper plan whose tapers fall far below eps inside their
+    supports (N = 3072 at 256 Hz, Q 4.1, 15 rows from 20.9 Hz): eps floors
+    every window, so the single-tile inverse of every row stays within the
+    conditioning bar of the oracle's (with only the zeros replaced it missed
+    by order 1 in both precisions)."""
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    fs, n, q, fmin, fmax, R = 256.0, 3072, 4.107609620941872, 20.927358999587156, 128.0, 15
+    eps = EPS[precision]
+    gp = qt.Plan(fs, n, q, fmin, fmax, R, window="planck", window_param=0.25, precision=precision, window_eps=eps)
+    op = o.OraclePlan(fs=fs, n=n, q=q, f_min=fmin, f_max=fmax, rows=R, window=o.WIN_PLANCK, window_param=0.25,
+                      eps=eps)
+    x = np.stack([synthetic.injected_segment(n, fs, synthetic.rng_for(16, i))[0] for i in range(2)])
+    cdt = torch.complex128 if precision == "fp64" else torch.complex64
+    Yo = op.forward(x.astype(np.float32).astype(np.float64) if precision == "fp32" else x)
+    Yc = torch.from_numpy(Yo).to(dtype=cdt, device="cuda")
+    Ych = Yc.cpu().numpy().astype(np.complex128)
+    bar = 2000.0 * UNIT[precision] / eps
+    worst = max(rel_rows(gp.tile_inverse(Yc, k).cpu().numpy(), op.tile_inverse(Ych, k)).max() for k in range(R))
+    print(f"planck {precision}: single-tile inverse vs oracle, worst row {worst:.3e} (bar {bar:.1e})", flush=True)
+    assert worst <= bar

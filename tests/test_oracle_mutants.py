@@ -42,6 +42,8 @@ MUTANTS = [
      "x[t] = a[static_cast<size_t>(t)].real();"),
     ("grid_exponent_off", "static_cast<double>(k) / static_cast<double>(nrows - 1)",
      "static_cast<double>(k) / static_cast<double>(nrows)"),
+    # the stop-band value replacing only exact zeros (a taper's tails below eps kept)
+    ("eps_only_on_zeros", "if (eps > 0.0 && v < eps) v = eps;", "if (eps > 0.0 && v == 0.0) v = eps;"),
 ]
 
 

@@ -486,10 +486,12 @@ def test_regularised_windows_and_single_tile_recovery():
     p0 = o.OraclePlan(**kw)
     W, W0 = p.windows(), p0.windows()
     assert np.all(W > 0) and p.N_out >= p.n // 2 + 1
-    # inside the support the shape is the plain window up to the normalisation;
-    # elsewhere (where the shape is zero) the value is eps times that factor
+    # where the shape is at least eps it is the plain window up to the
+    # normalisation; elsewhere (the stop band, the support's end points and
+    # the tails below eps) the value is eps times that factor
     for k in range(p.R):
-        on = W0[k] > 0
+        on = W0[k] >= eps * W0[k].max()
+        assert (~on).sum() > p.n // 2 - (p.row_table()["hi"][k] - p.row_table()["lo"][k])   # tails included
         ratio = W[k, on] / W0[k, on]
         assert np.allclose(ratio, ratio[0], rtol=1e-13)
         # the bisquare shape peaks at 1, so the plain window's peak is 1/||shape||
@@ -501,6 +503,29 @@ def test_regularised_windows_and_single_tile_recovery():
     # the plain windows vanish at their support ends: no division possible
     with pytest.raises(ValueError):
         p0.tile_inverse(p0.forward(x), 2)
+
+
+def test_regularised_taper_tails_floored():
+    """A Planck taper falls far below any eps inside its support (down to
+    underflow near the ends). With eps read as a floor every window is at
+    least eps times its peak, so the single-tile inverse amplifies rounding
+    by at most about 1/eps: FP64 recovery of the signal from each of several
+    tiles within 1e-15/eps, on rows whose plain taper has values below
+    eps/10 of its peak (with only the zeros replaced, row 11's smallest value,
+    6e-9 of its peak, would amplify rounding about 200 times more)."""
+    kw = dict(fs=256.0, n=2048, q=6.0, f_min=8.0, f_max=120.0, rows=12, window=o.WIN_PLANCK, window_param=0.25)
+    eps = 1e-5
+    p = o.OraclePlan(eps=eps, **kw)
+    p0 = o.OraclePlan(**kw)
+    W, W0 = p.windows(), p0.windows()
+    for k in range(p.R):
+        assert W[k].min() >= eps * W[k].max() * (1 - 1e-12)
+    tiny = [k for k in range(p.R) if np.any((W0[k] > 0) & (W0[k] < 0.1 * eps * W0[k].max()))]
+    assert tiny, "no row with a taper tail far below eps"
+    x = np.random.default_rng(43).standard_normal((2, p.n))
+    Y = p.forward(x)
+    for k in tiny + [0]:
+        assert rel(p.tile_inverse(Y, k), x) < 1e-15 / eps, k
 
 
 @pytest.mark.parametrize("n,f_min,f_max", [(256, 8.0, 50.0), (384, 5.0, 60.0), (640, 3.0, 62.0)])
