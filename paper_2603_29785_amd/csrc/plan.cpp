@@ -29,8 +29,14 @@ double shape(int32_t kind, double x, double a) {
   }
   if (kind == QTAM_WIN_HANN) return 0.5 + 0.5 * std::cos(0.5 * kTwoPi * x);
   if (kind == QTAM_WIN_KAISER) {
+    // I0(beta) once per beta (every bin of a plane shares it)
+    thread_local double beta = std::numeric_limits<double>::quiet_NaN(), i0_beta = 1.0;
+    if (!(a == beta)) {
+      beta = a;
+      i0_beta = std::cyl_bessel_i(0.0, a);
+    }
     const double r = std::sqrt(std::max(0.0, (1.0 - ax) * (1.0 + ax)));
-    return std::cyl_bessel_i(0.0, a * r) / std::cyl_bessel_i(0.0, a);
+    return std::cyl_bessel_i(0.0, a * r) / i0_beta;
   }
   if (kind == QTAM_WIN_TUKEY) {
     const double flat = 1.0 - a;
@@ -172,9 +178,17 @@ qtam_status build_host_plan(const qtam_params& p, HostPlan& hp) {
 
     double e2 = 0.0;
     const size_t base = hp.win.size();
+    // every shape depends on |x| only: each offset |c - s| is evaluated once
+    // (x = -j/h and j/h give the same |x| bits)
+    std::vector<double> at(static_cast<size_t>(h) + 1, -1.0);
     for (int64_t c = a; c <= b; ++c) {
       const bool inside = c >= s - h && c <= s + h;
-      double w = inside ? shape(plane.window, static_cast<double>(c - s) / static_cast<double>(h), plane.param) : 0.0;
+      double w = 0.0;
+      if (inside) {
+        const size_t j = static_cast<size_t>(c >= s ? c - s : s - c);
+        if (at[j] < 0.0) at[j] = shape(plane.window, static_cast<double>(j) / static_cast<double>(h), plane.param);
+        w = at[j];
+      }
       if (hp.eps > 0.0 && w < hp.eps) w = hp.eps;   // floor: the stop band, end points, tails below eps
       hp.win.push_back(w);
       e2 += w * w;

@@ -559,3 +559,77 @@ def test_random_plans_parity(torch_dev, spec, precision):
     e_x = rel_rows(xr, op.inverse(Yc)).max()
     print(f"  coef {e_y:.3e}, inverse {e_x:.3e}", flush=True)
     assert e_y <= TOL[precision] and e_x <= TOL[precision]
+
+
+def random_mode_plans(seed, count):
+    """Seeded random plans over the cap modes (cover, paper, none, manual),
+    the normalisations, explicit frequency lists with a duplicated centre and
+    mask floors; frames with kappa up to 1e8."""
+    import paper_2603_29785_amd as qt
+    rng = np.random.default_rng(seed)
+    caps = [("cover", o.CAP_COVER), ("paper", o.CAP_PAPER), ("none", o.CAP_NONE), ("manual", o.CAP_MANUAL)]
+    norms = [("unit_energy", o.NORM_UNIT_ENERGY), ("paper_inv_energy", o.NORM_PAPER_INV_ENERGY),
+             ("none", o.NORM_NONE)]
+    wins = [("bisquare", o.WIN_BISQUARE, 0.0), ("hann", o.WIN_HANN, 0.0), ("kaiser", o.WIN_KAISER, 5.0),
+            ("tukey", o.WIN_TUKEY, 0.4), ("planck", o.WIN_PLANCK, 0.25)]
+    out = []
+    while len(out) < count:
+        r = int(rng.choice([1, 3, 5]))
+        n = r * 2 ** int(rng.integers(10, 17 if r == 1 else 14))
+        fs = float(rng.choice([256.0, 1024.0, 4096.0]))
+        nyq = fs / 2
+        fmin = float(rng.uniform(0.01, 0.2)) * nyq
+        fmax = float(rng.choice([nyq, rng.uniform(0.4, 0.95) * nyq]))
+        if fmin < 2 * fs / n:
+            continue
+        rows = int(rng.integers(4, 80))
+        q = float(rng.uniform(2.0, 24.0))
+        cap = caps[int(rng.integers(4))]
+        norm = norms[int(rng.integers(3))]
+        win = wins[int(rng.integers(5))]
+        freqs = None
+        if rng.random() < 0.25:
+            freqs = np.sort(rng.uniform(fmin, fmax, rows))
+            freqs[rows // 2] = freqs[rows // 2 - 1]
+        max_window = int(rng.integers(3, 400)) if cap[0] == "manual" else 0
+        floor = float(rng.choice([1e-6, 1e-3, 0.0]))
+        kw = dict(window=win[0], window_param=win[2], cap_mode=cap[0], max_window=max_window, norm_mode=norm[0],
+                  p_floor_rel=floor, freqs=freqs)
+        try:
+            host = qt.Plan(fs, n, q, fmin, fmax, rows, host_only=True, **kw)
+        except qt.QtamError:
+            continue
+        if not (host.info.frame_A > 0) or host.info.frame_B / host.info.frame_A > 1e8:
+            continue
+        okw = dict(window=win[1], window_param=win[2], cap_mode=cap[1], max_window=max_window, norm_mode=norm[1],
+                   p_floor_rel=floor, freqs=freqs)
+        out.append((fs, n, q, fmin, fmax, rows, kw, okw, host.info.frame_B / host.info.frame_A))
+    return out
+
+
+MODES = random_mode_plans(9101, 8)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("spec", MODES, ids=[f"N{s[1]}_R{s[5]}_{s[6]['cap_mode']}_{s[6]['norm_mode']}" for s in MODES])
+def test_random_mode_plans_parity(torch_dev, spec, precision):
+    """Cap modes, normalisations, explicit grids and mask floors on seeded
+    random plans: coefficients at the bars, the inverse at the bars scaled by
+    sqrt(kappa / 1e4) above kappa = 1e4 (reading 22)."""
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    fs, n, q, fmin, fmax, rows, kw, okw, kappa = spec
+    gp = qt.Plan(fs, n, q, fmin, fmax, rows, precision=precision, **kw)
+    op = o.OraclePlan(fs=fs, n=n, q=q, f_min=fmin, f_max=fmax, rows=rows, **okw)
+    assert gp.N_out == op.N_out and gp.R == op.R
+    x = host_input(np.stack([synthetic.injected_segment(n, fs, synthetic.rng_for(71, j))[0] for j in range(2)]),
+                   precision)
+    Yo = op.forward(x)
+    e_y = rel_rows(gp.forward(to_dev(torch, x, precision)).cpu().numpy(), Yo).max()
+    Yc = Yo.astype(np.complex64).astype(np.complex128) if precision == "fp32" else Yo
+    cdt = torch.complex64 if precision == "fp32" else torch.complex128
+    e_x = rel_rows(gp.inverse(torch.from_numpy(Yc).to(cdt).cuda()).cpu().numpy(), op.inverse(Yc)).max()
+    scale = max(1.0, math.sqrt(kappa / 1e4))
+    print(f"modes {kw['cap_mode']} {kw['norm_mode']} kappa {kappa:.2g} {precision}: coef {e_y:.2e} inverse {e_x:.2e}",
+          flush=True)
+    assert e_y <= TOL[precision] and e_x <= TOL[precision] * scale

@@ -114,3 +114,42 @@ def test_planck_taper_tails_single_tile(torch_dev, precision):
     worst = max(rel_rows(gp.tile_inverse(Yc, k).cpu().numpy(), op.tile_inverse(Ych, k)).max() for k in range(R))
     print(f"planck {precision}: single-tile inverse vs oracle, worst row {worst:.3e} (bar {bar:.1e})", flush=True)
     assert worst <= bar
+
+
+def _random_regularised():
+    import test_gpu_parity as tp
+    return tp.random_plans(5102, 8, log2n=(11, 16), log2n_odd=(10, 14), row_range=(3, 25), kinds=(0,))
+
+
+RANDOM_REG = _random_regularised()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("spec", RANDOM_REG, ids=[f"N{s[1]}_R{s[5]}_{s[6]}" for s in RANDOM_REG])
+def test_random_regularised_plans(torch_dev, spec, precision):
+    """Seeded random plans (every window, N = r 2^k) with the stop band:
+    coefficients and inverse at the bars, and the single-tile inverse of the
+    first, middle and last rows within the conditioning bar of the oracle's
+    (the sweep that found the taper tails of reading 21)."""
+    torch = torch_dev
+    import paper_2603_29785_amd as qt
+    fs, n, q, fmin, fmax, rows, wname, wid, wparam, _ = spec
+    eps = EPS[precision]
+    gp = qt.Plan(fs, n, q, fmin, fmax, rows, window=wname, window_param=wparam, precision=precision, window_eps=eps)
+    op = o.OraclePlan(fs=fs, n=n, q=q, f_min=fmin, f_max=fmax, rows=rows, window=wid, window_param=wparam, eps=eps)
+    x = np.stack([synthetic.injected_segment(n, fs, synthetic.rng_for(62, j))[0] for j in range(2)])
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    cdt = torch.complex128 if precision == "fp64" else torch.complex64
+    xd = torch.from_numpy(x).to(dtype=dt, device="cuda")
+    xh = xd.double().cpu().numpy()
+    Yo = op.forward(xh)
+    e_y = rel_rows(gp.forward(xd).cpu().numpy(), Yo).max()
+    Yc = torch.from_numpy(Yo).to(dtype=cdt, device="cuda")
+    Ych = Yc.cpu().numpy().astype(np.complex128)
+    e_x = rel_rows(gp.inverse(Yc).cpu().numpy(), op.inverse(Ych)).max()
+    bar = 2000.0 * UNIT[precision] / eps
+    e_t = max(rel_rows(gp.tile_inverse(Yc, k).cpu().numpy(), op.tile_inverse(Ych, k)).max()
+              for k in (0, rows // 2, rows - 1))
+    print(f"random regularised {spec[:6]} {wname} {precision}: coef {e_y:.2e} inverse {e_x:.2e} tile {e_t:.2e} "
+          f"(bar {bar:.1e})", flush=True)
+    assert e_y <= TOL[precision] and e_x <= TOL[precision] and e_t <= bar
